@@ -1,0 +1,180 @@
+/*
+ * scn.h -- C ABI of libscn, a gfx950 (MI355X) implementation of the
+ * data-parallel pixel stage that Scanner computation graphs run over frames
+ * sampled from a video table (Poms et al., "Scanner: Efficient Video
+ * Analysis at Scale", SIGGRAPH 2018).
+ *
+ * Concepts (paper Sec. 3):
+ *   - a video is a table with one row per frame (Sec. 3, "Videos as logical
+ *     tables"); here a table is a column of decoded NV12 frames resident in
+ *     device memory;
+ *   - sampling operations select rows by stride, index list or range
+ *     (Sec. 3.2, "Sampling/spacing operations"); ranges also act as slices,
+ *     boundaries that reset stencils (Sec. 3.2, "Slicing");
+ *   - optical flow is a stencil S[0,1] operation on the sampled sequence
+ *     (Sec. 3.2, "Stencil operations"), i.e. between consecutive sampled
+ *     rows of one slice;
+ *   - a job binds an operation to a table and its sampling (Sec. 3.1);
+ *   - operations run over batches of elements (Sec. 3.3) and only the
+ *     sampled elements are ever read or computed (Sec. 4.2, unneeded element
+ *     elimination);
+ *   - scratch comes from a caller-owned memory pool (Sec. 4.1, custom GPU
+ *     memory pools): no call allocates or frees device memory.
+ *
+ * Conventions shared by every entry point:
+ *   - Every pointer named "device" is a HIP device pointer on the current
+ *     device; "host" pointers are read before the call returns.
+ *   - Every call is asynchronous on the given stream (a hipStream_t; NULL is
+ *     the null stream).  Results are valid after the stream is synchronised.
+ *   - Validation is complete before anything is enqueued.  On error nothing
+ *     is enqueued, the status is negative and scn_last_error() explains why.
+ *     HIP launch failures return SCN_EHIP; device faults surface at the
+ *     caller's synchronisation.
+ *   - Empty samplings (no rows, or no pairs for flow) return SCN_OK and
+ *     enqueue nothing.
+ *   - The caller owns every buffer.  `ws` is scratch device memory of
+ *     `ws_bytes` bytes (size it with scn_workspace_bytes); its contents
+ *     persist between calls.  The library uploads a small plan (row and pair
+ *     tables) to the start of `ws` and skips the upload when the same plan
+ *     was last uploaded to the same `ws`; a caller that writes into `ws`
+ *     itself must call scn_ws_forget(ws) first.  Calls that share one `ws`
+ *     must be ordered on one stream.
+ */
+#ifndef SCN_H
+#define SCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* scn_stream_t; /* hipStream_t */
+
+typedef enum {
+  SCN_OK = 0,
+  SCN_EINVAL = -1,        /* an argument is invalid (null pointer, bad size, bad sampling) */
+  SCN_EUNSUPPORTED = -2,  /* valid but not supported (odd width/height, too many levels) */
+  SCN_ENOSPACE = -3,      /* ws_bytes is smaller than the minimum the call needs */
+  SCN_EHIP = -4           /* a HIP runtime call failed */
+} scn_status;
+
+/* A video table: n_frames decoded NV12 uint8 frames in device memory.
+ * Row f starts at frames + f * frame_bytes and holds the Y plane (height rows
+ * of pitch bytes, the first width bytes used) followed by the interleaved
+ * chroma plane (height/2 rows of pitch bytes: U0 V0 U1 V1 ...).
+ * width and height are even and >= 2; pitch >= width;
+ * frame_bytes >= pitch * height * 3 / 2. */
+typedef struct {
+  const uint8_t* frames; /* device */
+  int32_t width, height, pitch, reserved;
+  int64_t frame_bytes, n_frames;
+} scn_table;
+
+typedef enum { SCN_STRIDE = 0, SCN_GATHER = 1, SCN_RANGE = 2 } scn_sample_kind;
+
+/* Sampling spec (paper Sec. 3.2; access patterns of Sec. 5.1.1).
+ *   STRIDE: rows start, start+step, ... < stop (0 <= start <= stop <= n_frames, step >= 1).
+ *   GATHER: idx holds n strictly increasing rows in [0, n_frames).
+ *   RANGE:  idx holds n windows as 2n values begin_0, end_0, begin_1, ...;
+ *           half-open, ascending and disjoint.  Each window is a slice:
+ *           flow pairs never cross two windows.
+ * idx is host memory. */
+typedef struct {
+  int32_t kind, reserved;
+  int64_t start, step, stop;
+  const int64_t* idx; /* host */
+  int64_t n;
+} scn_sampling;
+
+typedef struct {
+  const scn_table* table;       /* host */
+  const scn_sampling* sampling; /* host */
+} scn_job;
+
+/* Pyramidal Horn-Schunck parameters (Horn & Schunck 1981, coarse to fine):
+ * `levels` >= 1 pyramid levels (each level halves the size, rounding up;
+ * the coarsest level must be at least 2x2), smoothness weight `alpha` > 0 in
+ * luma code units, `iters` >= 0 Jacobi iterations at every level.
+ * `sweeps_per_pass` (0 = autotuned) and `tile_rows` (0 = autotuned) select
+ * the Jacobi kernel's temporal blocking and tile height; every choice gives
+ * bitwise identical results. */
+typedef struct {
+  int32_t levels;
+  float alpha;
+  int32_t iters;
+  int32_t sweeps_per_pass;
+  int32_t tile_rows;
+  int32_t reserved;
+} scn_flow_params;
+
+enum { SCN_RGB24 = 0, SCN_GRAY8 = 1 };
+enum { SCN_OP_CONVERT = 0, SCN_OP_HIST = 1, SCN_OP_FLOW = 2, SCN_OP_SURROGATE = 3 };
+
+/* Number of sampled rows M of a job, or a negative scn_status. */
+int64_t scn_count_rows(const scn_job* job);
+
+/* Number of flow pairs P of a job (consecutive sampled rows within each
+ * slice; Sec. 3.2 stencil after sampling), or a negative scn_status. */
+int64_t scn_count_pairs(const scn_job* job);
+
+/* Minimum workspace for an operation (SCN_OP_*) over `n_jobs` jobs; for
+ * SCN_OP_CONVERT and SCN_OP_HIST n_jobs must be 1.  Returns 0 on invalid
+ * arguments (see scn_last_error). */
+size_t scn_workspace_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p);
+
+/* Gather the sampled rows of one job and convert them from NV12 to RGB24
+ * (BT.601 limited range, Q14 fixed point, chroma replicated 2x2) or take
+ * their luma (GRAY8), then resize bilinearly to out_w x out_h with
+ * half-pixel centres and 8-bit weights (no resize when the sizes match).
+ * This is the format conversion Sec. 4.3 counts as decoder post-processing
+ * plus the Resize map of Sec. 3.1, applied only to sampled rows.
+ * out: device, [M][out_h][out_w][3] (RGB24, R first) or [M][out_h][out_w]
+ * (GRAY8), uint8, row-major, no padding.  out_w, out_h >= 1. */
+scn_status scn_sample_convert(const scn_job* job, int32_t out_w, int32_t out_h, int32_t fmt,
+                              uint8_t* out, void* ws, size_t ws_bytes, scn_stream_t stream);
+
+/* HIST (Sec. 5.1.2): per sampled row, 16 uniform bins of width 16 per R, G, B
+ * channel of the full-resolution BT.601 conversion.
+ * hist: device, uint32 [M][3][16] (channel-major), overwritten. */
+scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_bytes,
+                    scn_stream_t stream);
+
+/* FLOW (Sec. 3.2 stencil S[0,1], Sec. 5.1.2): dense pyramidal Horn-Schunck
+ * optical flow, FP32, between consecutive sampled rows of each slice of
+ * every job.  Jobs may differ in resolution; all of their pairs are
+ * computed by one batch of launches.  Each sampled frame's pyramid is built
+ * once and shared by the (at most two) pairs that use it.
+ * flow[j]: device, float [P_j][2][H_j][W_j] (u plane then v plane, pixels
+ * at full resolution, I1(x) ~ I2(x + (u, v))); may be NULL when P_j == 0. */
+scn_status scn_flow(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p,
+                    float* const* flow, void* ws, size_t ws_bytes, scn_stream_t stream);
+
+/* Kernel timing for diagnostics and benchmarks.  scn_timing_enable(1, n)
+ * creates a pool of 2n HIP events; while enabled, every kernel launch of the
+ * library is bracketed by two events recorded on its stream (at most n
+ * launches until the next scn_timing_reset).  scn_timing_read synchronises
+ * those events and returns the summed duration and launch count of one
+ * kernel class ("hist16", "nv12_rgb24", "nv12_resize", "luma_copy",
+ * "pyr_down", "hs_warp", "hs_coef", "hs_jacobi"); it returns SCN_ENOSPACE if
+ * launches were dropped because the pool was full.  Not thread-safe with
+ * respect to concurrent enable/reset. */
+scn_status scn_timing_enable(int32_t enable, int32_t max_launches);
+scn_status scn_timing_reset(void);
+scn_status scn_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+
+/* Forget any plan cached for `ws` (call after writing into ws yourself). */
+void scn_ws_forget(const void* ws);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* scn_last_error(void);
+
+/* Library version string. */
+const char* scn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCN_H */

@@ -1,0 +1,329 @@
+"""Python binding of libscn (ctypes; argument marshalling only).
+
+Every step of the pixel stage runs in libscn's HIP kernels.  PyTorch is used
+for device memory (input tables, outputs, the workspace pool) and for the
+stream handle; nothing here computes pixels.  Importing the package does not
+need a GPU; calling into the library needs the built libscn.so and fails
+loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libscn.so")
+
+SCN_OK, SCN_EINVAL, SCN_EUNSUPPORTED, SCN_ENOSPACE, SCN_EHIP = 0, -1, -2, -3, -4
+SCN_STRIDE, SCN_GATHER, SCN_RANGE = 0, 1, 2
+SCN_RGB24, SCN_GRAY8 = 0, 1
+SCN_OP_CONVERT, SCN_OP_HIST, SCN_OP_FLOW, SCN_OP_SURROGATE = 0, 1, 2, 3
+
+_STATUS_NAMES = {SCN_EINVAL: "SCN_EINVAL", SCN_EUNSUPPORTED: "SCN_EUNSUPPORTED", SCN_ENOSPACE: "SCN_ENOSPACE",
+                 SCN_EHIP: "SCN_EHIP"}
+
+
+class ScnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class CTable(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("reserved", ctypes.c_int32), ("frame_bytes", ctypes.c_int64),
+                ("n_frames", ctypes.c_int64)]
+
+
+class CSampling(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("start", ctypes.c_int64),
+                ("step", ctypes.c_int64), ("stop", ctypes.c_int64), ("idx", ctypes.POINTER(ctypes.c_int64)),
+                ("n", ctypes.c_int64)]
+
+
+class CJob(ctypes.Structure):
+    _fields_ = [("table", ctypes.POINTER(CTable)), ("sampling", ctypes.POINTER(CSampling))]
+
+
+class CFlowParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("alpha", ctypes.c_float), ("iters", ctypes.c_int32),
+                ("sweeps_per_pass", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# Every symbol declared in include/scn.h (checked by the CPU test suite).
+EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
+           "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
+           "scn_timing_reset", "scn_timing_read"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libscn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libscn.so is not built (%s); run __graft_entry__.build() or "
+                           "python -m paper_1805_07339_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.scn_count_rows.argtypes = [P(CJob)]
+    L.scn_count_rows.restype = ctypes.c_int64
+    L.scn_count_pairs.argtypes = [P(CJob)]
+    L.scn_count_pairs.restype = ctypes.c_int64
+    L.scn_workspace_bytes.argtypes = [ctypes.c_int32, P(CJob), ctypes.c_int32, P(CFlowParams)]
+    L.scn_workspace_bytes.restype = ctypes.c_size_t
+    L.scn_sample_convert.argtypes = [P(CJob), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                     ctypes.c_size_t, vp]
+    L.scn_sample_convert.restype = ctypes.c_int
+    L.scn_hist.argtypes = [P(CJob), vp, vp, ctypes.c_size_t, vp]
+    L.scn_hist.restype = ctypes.c_int
+    L.scn_flow.argtypes = [P(CJob), ctypes.c_int32, P(CFlowParams), P(vp), vp, ctypes.c_size_t, vp]
+    L.scn_flow.restype = ctypes.c_int
+    L.scn_ws_forget.argtypes = [vp]
+    L.scn_ws_forget.restype = None
+    L.scn_last_error.argtypes = []
+    L.scn_last_error.restype = ctypes.c_char_p
+    L.scn_version.argtypes = []
+    L.scn_version.restype = ctypes.c_char_p
+    L.scn_timing_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.scn_timing_enable.restype = ctypes.c_int
+    L.scn_timing_reset.argtypes = []
+    L.scn_timing_reset.restype = ctypes.c_int
+    L.scn_timing_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    L.scn_timing_read.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != SCN_OK:
+        raise ScnError(status, lib().scn_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# tables, sampling specs, jobs
+
+
+@dataclass
+class Table:
+    """A column of decoded NV12 frames: uint8 tensor [n_frames, frame_bytes] (or any
+    tensor whose memory is laid out that way) with frame geometry."""
+    frames: torch.Tensor
+    width: int
+    height: int
+    pitch: int
+    frame_bytes: int
+    n_frames: int
+
+    @staticmethod
+    def from_tensor(frames: torch.Tensor, width: int, height: int, pitch: Optional[int] = None) -> "Table":
+        pitch = width if pitch is None else pitch
+        if frames.dtype != torch.uint8:
+            raise TypeError("table frames must be uint8")
+        n = frames.shape[0]
+        fb = frames.stride(0) * frames.element_size() if frames.dim() > 1 else frames.numel()
+        return Table(frames, width, height, pitch, fb, n)
+
+    def c(self) -> CTable:
+        return CTable(self.frames.data_ptr(), self.width, self.height, self.pitch, 0, self.frame_bytes,
+                      self.n_frames)
+
+
+class Sampling:
+    """Stride / gather / range sampling (host-side spec)."""
+
+    def __init__(self, kind: int, start: int = 0, step: int = 1, stop: int = 0, idx: Sequence[int] = ()):
+        self.kind, self.start, self.step, self.stop = kind, start, step, stop
+        self.idx = [int(v) for v in idx]
+        self._arr = (ctypes.c_int64 * max(len(self.idx), 1))(*self.idx)
+
+    @staticmethod
+    def stride(step: int, start: int = 0, stop: Optional[int] = None, n_frames: Optional[int] = None) -> "Sampling":
+        if stop is None:
+            stop = n_frames
+        return Sampling(SCN_STRIDE, start, step, stop)
+
+    @staticmethod
+    def gather(rows: Sequence[int]) -> "Sampling":
+        return Sampling(SCN_GATHER, idx=rows)
+
+    @staticmethod
+    def range(windows: Sequence[Tuple[int, int]]) -> "Sampling":
+        flat = [v for w in windows for v in w]
+        s = Sampling(SCN_RANGE, idx=flat)
+        s.n_windows = len(windows)
+        return s
+
+    def c(self) -> CSampling:
+        n = len(self.idx) // 2 if self.kind == SCN_RANGE else len(self.idx)
+        return CSampling(self.kind, 0, self.start, self.step, self.stop,
+                         ctypes.cast(self._arr, ctypes.POINTER(ctypes.c_int64)), n)
+
+
+class Job:
+    def __init__(self, table: Table, sampling: Sampling):
+        self.table, self.sampling = table, sampling
+        self._ct = table.c()
+        self._cs = sampling.c()
+        self.cjob = CJob(ctypes.pointer(self._ct), ctypes.pointer(self._cs))
+
+
+def _jobs_array(jobs: Sequence[Job]):
+    arr = (CJob * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.cjob
+    return arr
+
+
+def flow_params(levels: int = 4, alpha: float = 10.0, iters: int = 50, sweeps_per_pass: int = 0,
+                tile_rows: int = 0) -> CFlowParams:
+    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_rows, 0)
+
+
+def count_rows(job: Job) -> int:
+    n = lib().scn_count_rows(ctypes.byref(job.cjob))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def count_pairs(job: Job) -> int:
+    n = lib().scn_count_pairs(ctypes.byref(job.cjob))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def workspace_bytes(op: int, jobs: Sequence[Job], params: Optional[CFlowParams] = None) -> int:
+    arr = _jobs_array(jobs)
+    n = lib().scn_workspace_bytes(op, arr, len(jobs), ctypes.byref(params) if params is not None else None)
+    if n == 0:
+        raise ScnError(SCN_EINVAL, lib().scn_last_error().decode())
+    return int(n)
+
+
+# ---------------------------------------------------------------------------
+# workspace pool (caller-owned scratch; the library never allocates)
+
+
+class Workspace:
+    """A growable device scratch buffer, one per (device, name)."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            if self.buf is not None:
+                lib().scn_ws_forget(self.buf.data_ptr())
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_pools = {}
+
+
+def _ws(device, nbytes: int, name: str = "default") -> torch.Tensor:
+    key = (str(device), name)
+    if key not in _pools:
+        _pools[key] = Workspace(device)
+    return _pools[key].get(nbytes)
+
+
+# ---------------------------------------------------------------------------
+# operations
+
+
+def hist(job: Job, out: Optional[torch.Tensor] = None, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-sampled-row 16-bin R, G, B histograms -> int32 tensor [M, 3, 16] (uint32 counts)."""
+    m = count_rows(job)
+    dev = job.table.frames.device
+    if out is None:
+        out = torch.empty((m, 3, 16), dtype=torch.int32, device=dev)
+    if m == 0:
+        return out
+    need = workspace_bytes(SCN_OP_HIST, [job])
+    w = ws if ws is not None else _ws(dev, need)
+    _check(lib().scn_hist(ctypes.byref(job.cjob), out.data_ptr(), w.data_ptr(), w.numel(), _stream(stream)))
+    return out
+
+
+def sample_convert(job: Job, out_w: Optional[int] = None, out_h: Optional[int] = None, fmt: int = SCN_RGB24,
+                   out: Optional[torch.Tensor] = None, stream=None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gather + BT.601 convert (+ resize) -> uint8 [M, out_h, out_w, 3] (RGB24) or [M, out_h, out_w] (GRAY8)."""
+    t = job.table
+    out_w = t.width if out_w is None else out_w
+    out_h = t.height if out_h is None else out_h
+    m = count_rows(job)
+    if out is None:
+        shape = (m, out_h, out_w, 3) if fmt == SCN_RGB24 else (m, out_h, out_w)
+        out = torch.empty(shape, dtype=torch.uint8, device=t.frames.device)
+    if m == 0:
+        return out
+    need = workspace_bytes(SCN_OP_CONVERT, [job])
+    w = ws if ws is not None else _ws(t.frames.device, need)
+    _check(lib().scn_sample_convert(ctypes.byref(job.cjob), out_w, out_h, fmt, out.data_ptr(), w.data_ptr(),
+                                    w.numel(), _stream(stream)))
+    return out
+
+
+def flow(jobs: Sequence[Job], params: Optional[CFlowParams] = None, outs: Optional[List[torch.Tensor]] = None,
+         stream=None, ws: Optional[torch.Tensor] = None, ws_bytes: Optional[int] = None) -> List[torch.Tensor]:
+    """Pyramidal Horn-Schunck flow for every job -> list of float32 [P_j, 2, H_j, W_j]."""
+    params = flow_params() if params is None else params
+    if outs is None:
+        outs = []
+        for j in jobs:
+            p = count_pairs(j)
+            outs.append(torch.empty((p, 2, j.table.height, j.table.width), dtype=torch.float32,
+                                    device=j.table.frames.device))
+    arr = _jobs_array(jobs)
+    ptrs = (ctypes.c_void_p * len(jobs))(*[o.data_ptr() if o.numel() else None for o in outs])
+    if sum(o.shape[0] for o in outs) == 0:
+        return outs
+    if ws is None:
+        need = workspace_bytes(SCN_OP_FLOW, jobs, params) if ws_bytes is None else ws_bytes
+        ws = _ws(jobs[0].table.frames.device, need)
+    nbytes = ws.numel() if ws_bytes is None else min(ws_bytes, ws.numel())
+    _check(lib().scn_flow(arr, len(jobs), ctypes.byref(params), ptrs, ws.data_ptr(), nbytes, _stream(stream)))
+    return outs
+
+
+def timing_enable(on: bool = True, max_launches: int = 65536):
+    _check(lib().scn_timing_enable(1 if on else 0, max_launches))
+
+
+def timing_reset():
+    _check(lib().scn_timing_reset())
+
+
+def timing_read(kernel: str) -> Tuple[float, int]:
+    """(total milliseconds, launches) recorded for one kernel class."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().scn_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def version() -> str:
+    return lib().scn_version().decode()

@@ -1,0 +1,52 @@
+// Shared device/host helpers for libscn's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "plan.hpp"
+
+namespace scn {
+
+// Map a HIP error to SCN_EHIP with a message naming the failing step.
+inline scn_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return SCN_EHIP;
+}
+
+#define SCN_HIP(call, what)                          \
+  do {                                               \
+    hipError_t _e = (call);                          \
+    if (_e != hipSuccess) return ::scn::hip_fail(_e, what); \
+  } while (0)
+
+#define SCN_LAUNCHED(what)                                   \
+  do {                                                       \
+    hipError_t _e = hipGetLastError();                       \
+    if (_e != hipSuccess) return ::scn::hip_fail(_e, what);  \
+  } while (0)
+
+// Upload `bytes` to the start of `ws` unless exactly these bytes were the
+// last plan uploaded there.  The copy is ordered on `stream`.
+scn_status upload_plan(void* ws, const void* bytes, size_t n, hipStream_t stream);
+void forget_plan(const void* ws);
+
+// Optional per-kernel timing (diagnostics): while enabled, launches wrapped
+// in a KernelTimer are bracketed by HIP events recorded on their stream.
+// Events come from a pool created when timing is enabled.
+bool timing_on();
+int timing_begin(const char* name, hipStream_t s);   // returns a record id or -1
+void timing_end(int id, hipStream_t s);
+
+struct KernelTimer {
+  int id;
+  hipStream_t s;
+  KernelTimer(const char* name, hipStream_t st) : id(timing_on() ? timing_begin(name, st) : -1), s(st) {}
+  ~KernelTimer() {
+    if (id >= 0) timing_end(id, s);
+  }
+};
+
+}  // namespace scn

@@ -1,0 +1,330 @@
+// Pyramidal Horn-Schunck optical flow (Horn & Schunck 1981) between
+// consecutive sampled frames -- the FLOW stencil S[0,1] of the Scanner paper
+// (Sec. 3.2, Sec. 5.1.2) -- for gfx950, FP32.
+//
+// Per pair and pyramid level (coarse to fine):
+//   warp:  u0, v0 = 2 * bilinear(coarser flow, x/2, y/2) (zero at the coarsest
+//          level); T = bilinear(I2, x + u0, y + v0), coordinates clamped.
+//   coef:  Ix = (Dx I1 + Dx T)/2, Iy likewise (central differences,
+//          clamp-to-edge), It' = (T - I1) - Ix u0 - Iy v0;
+//          with r = 1/sqrt(alpha^2 + Ix^2 + Iy^2) the kernel stores
+//          a = Ix r, b = Iy r, c = It' r, so that the Jacobi update
+//          u <- ubar - Ix (Ix ubar + Iy vbar + It') / (alpha^2 + Ix^2 + Iy^2)
+//          becomes u <- ubar - a s, v <- vbar - b s with s = a ubar + b vbar + c.
+//   jacobi: ubar = (sum of edge neighbours)/6 + (sum of diagonals)/12 with
+//          clamp-to-edge, written as ubar = (cu(x-1) + cu(x+1) + 2 p(x)) / 12
+//          where p(x) = u(x, y-1) + u(x, y+1) and cu(x) = 2 u(x, y) + p(x).
+//
+// Every Jacobi kernel evaluates exactly that sequence of FP32 operations per
+// pixel (explicit fmaf, no contraction), so all of them -- one sweep per
+// launch, or several sweeps per launch on register/LDS tiles with mirrored
+// halos -- produce bitwise identical flow.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "flow_plan.hpp"
+
+namespace scn {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct LevelGeom {
+  int32_t w, h;        // this level
+  int32_t cw, ch;      // coarser level (valid when has_coarse)
+  int32_t has_coarse;
+  int64_t n0;          // level-0 pixels (plane stride inside a pair's scratch)
+  int64_t lvl_off;     // float offset of this level inside a pyramid slot (l >= 1)
+  int32_t level;
+};
+
+struct ChunkPtrs {
+  const FrameDesc* frames;
+  const PairDesc* pairs;
+  float* pyr;            // pyramid slots, pyr_floats each
+  int64_t pyr_floats;
+  float* scratch;        // pair scratch, pair_floats each
+  int64_t pair_floats;
+  int64_t n_pairs, n_frames;
+};
+
+// (u, v) buffer codes: 0 and 1 are the pair's ping-pong buffers, 2 is the output.
+__device__ __forceinline__ float* uv_buf(const ChunkPtrs& c, int64_t pair, int code, int64_t n0) {
+  if (code == 2) return c.pairs[pair].out;
+  return c.scratch + pair * c.pair_floats + (int64_t)(kPlaneU0 + 2 * code) * n0;
+}
+__device__ __forceinline__ float* plane(const ChunkPtrs& c, int64_t pair, int k, int64_t n0) {
+  return c.scratch + pair * c.pair_floats + (int64_t)k * n0;
+}
+
+// Image of level l of frame slot f: u8 luma at level 0, float pyramid above.
+struct Img {
+  const uint8_t* y8;
+  const float* f;
+  int64_t pitch;
+  __device__ __forceinline__ float at(int32_t x, int32_t y) const {
+    return y8 ? (float)y8[(int64_t)y * pitch + x] : f[(int64_t)y * pitch + x];
+  }
+};
+__device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const LevelGeom& g) {
+  Img im;
+  if (g.level == 0) {
+    im.y8 = c.frames[f].y;
+    im.f = nullptr;
+    im.pitch = c.frames[f].pitch;
+  } else {
+    im.y8 = nullptr;
+    im.f = c.pyr + (int64_t)f * c.pyr_floats + g.lvl_off;
+    im.pitch = g.w;
+  }
+  return im;
+}
+
+__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return min(max(v, lo), hi); }
+
+// Bilinear sample at (X, Y) with X given as integer + fraction (exact
+// positions far from the origin); coordinates clamped to the image.
+template <typename F>
+__device__ __forceinline__ float bilinear_split(F at, int32_t w, int32_t h, int32_t xi, float xf, int32_t yi, float yf) {
+  int32_t x0, y0;
+  float fx, fy;
+  if (xi < 0) { x0 = 0; fx = 0.f; }
+  else if (xi >= w - 1) { x0 = w - 1; fx = 0.f; }
+  else { x0 = xi; fx = xf; }
+  if (yi < 0) { y0 = 0; fy = 0.f; }
+  else if (yi >= h - 1) { y0 = h - 1; fy = 0.f; }
+  else { y0 = yi; fy = yf; }
+  const int32_t x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+  const float top = (1.f - fx) * at(x0, y0) + fx * at(x1, y0);
+  const float bot = (1.f - fx) * at(x0, y1) + fx * at(x1, y1);
+  return (1.f - fy) * top + fy * bot;
+}
+
+// Start flow of a pixel: 2 * bilinear(coarse, x/2, y/2), or 0 at the coarsest level.
+__device__ __forceinline__ void start_flow(const float* cu, const float* cv, const LevelGeom& g, int32_t x, int32_t y,
+                                           float* u0, float* v0) {
+  if (!g.has_coarse) { *u0 = 0.f; *v0 = 0.f; return; }
+  const int32_t xi = x >> 1, yi = y >> 1;
+  const float xf = (x & 1) ? 0.5f : 0.f, yf = (y & 1) ? 0.5f : 0.f;
+  const int32_t cw = g.cw;
+  auto atu = [&](int32_t xx, int32_t yy) { return cu[(int64_t)yy * cw + xx]; };
+  auto atv = [&](int32_t xx, int32_t yy) { return cv[(int64_t)yy * cw + xx]; };
+  *u0 = 2.f * bilinear_split(atu, g.cw, g.ch, xi, xf, yi, yf);
+  *v0 = 2.f * bilinear_split(atv, g.cw, g.ch, xi, xf, yi, yf);
+}
+
+__device__ __forceinline__ float warp_sample(const Img& im, const LevelGeom& g, int32_t x, int32_t y, float u0, float v0) {
+  const float fu = floorf(u0), fv = floorf(v0);
+  const int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
+  const float xf = u0 - fu, yf = v0 - fv;
+  auto at = [&](int32_t xx, int32_t yy) { return im.at(xx, yy); };
+  return bilinear_split(at, g.w, g.h, xi, xf, yi, yf);
+}
+
+// ---------------------------------------------------------------------------
+// pyramid: level l = even samples of blur5(level l-1), [1,4,6,4,1]/16
+// horizontal then vertical, clamp-to-edge.  One thread per output pixel.
+__global__ void __launch_bounds__(kThreads) k_pyr_down(ChunkPtrs c, LevelGeom src, LevelGeom dst, int32_t bpf) {
+  const int64_t f = blockIdx.x / bpf;
+  const int64_t p = (int64_t)(blockIdx.x % bpf) * kThreads + threadIdx.x;
+  if (p >= (int64_t)dst.w * dst.h) return;
+  const int32_t x = (int32_t)(p % dst.w), y = (int32_t)(p / dst.w);
+  const Img im = level_img(c, (int32_t)f, src);
+  const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+  float acc = 0.f;
+  if (src.level == 0) {  // exact integer sums of u8 luma
+    const int ki[5] = {1, 4, 6, 4, 1};
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int32_t yy = clampi(2 * y + j - 2, 0, src.h - 1);
+      int hs = 0;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) hs += ki[i] * (int)im.y8[(int64_t)yy * im.pitch + clampi(2 * x + i - 2, 0, src.w - 1)];
+      s += ki[j] * hs;
+    }
+    acc = (float)s * (1.f / 256.f);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int32_t yy = clampi(2 * y + j - 2, 0, src.h - 1);
+      float hs = 0.f;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) hs += k[i] * im.f[(int64_t)yy * im.pitch + clampi(2 * x + i - 2, 0, src.w - 1)];
+      acc += k[j] * hs;
+    }
+  }
+  c.pyr[f * c.pyr_floats + dst.lvl_off + p] = acc;
+}
+
+// warp: T = I2 sampled at x + start flow.
+__global__ void __launch_bounds__(kThreads) k_hs_warp(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t bpp) {
+  const int64_t pr = blockIdx.x / bpp;
+  const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
+  if (p >= (int64_t)g.w * g.h) return;
+  const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
+  float u0 = 0.f, v0 = 0.f;
+  if (g.has_coarse) {
+    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
+    start_flow(cu, cu + (int64_t)g.cw * g.ch, g, x, y, &u0, &v0);
+  }
+  const Img i2 = level_img(c, c.pairs[pr].f2, g);
+  plane(c, pr, kPlaneW, g.n0)[p] = warp_sample(i2, g, x, y, u0, v0);
+}
+
+// coef: gradients, linearised constraint and scaled coefficients; writes the
+// start flow into the destination (u, v) buffer.
+__global__ void __launch_bounds__(kThreads) k_hs_coef(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
+                                                      float alpha2, int32_t bpp) {
+  const int64_t pr = blockIdx.x / bpp;
+  const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)g.w * g.h;
+  if (p >= n) return;
+  const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
+  float u0 = 0.f, v0 = 0.f;
+  if (g.has_coarse) {
+    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
+    start_flow(cu, cu + (int64_t)g.cw * g.ch, g, x, y, &u0, &v0);
+  }
+  const Img i1 = level_img(c, c.pairs[pr].f1, g);
+  const float* T = plane(c, pr, kPlaneW, g.n0);
+  const int32_t xl = max(x - 1, 0), xr = min(x + 1, g.w - 1);
+  const int32_t yu = max(y - 1, 0), yd = min(y + 1, g.h - 1);
+  const float d1x = (i1.at(xr, y) - i1.at(xl, y)) * 0.5f;
+  const float d1y = (i1.at(x, yd) - i1.at(x, yu)) * 0.5f;
+  const float dTx = (T[(int64_t)y * g.w + xr] - T[(int64_t)y * g.w + xl]) * 0.5f;
+  const float dTy = (T[(int64_t)yd * g.w + x] - T[(int64_t)yu * g.w + x]) * 0.5f;
+  const float Ix = 0.5f * (d1x + dTx);
+  const float Iy = 0.5f * (d1y + dTy);
+  const float It = T[p] - i1.at(x, y);
+  const float Itp = It - Ix * u0 - Iy * v0;
+  const float den = alpha2 + Ix * Ix + Iy * Iy;
+  const float r = 1.0f / sqrtf(den);
+  plane(c, pr, kPlaneA, g.n0)[p] = Ix * r;
+  plane(c, pr, kPlaneB, g.n0)[p] = Iy * r;
+  plane(c, pr, kPlaneC, g.n0)[p] = Itp * r;
+  float* dst = uv_buf(c, pr, dst_code, g.n0);
+  dst[p] = u0;
+  dst[n + p] = v0;
+}
+
+// The per-pixel Jacobi update shared by every Jacobi kernel.
+//   pu = u(x, y-1) + u(x, y+1); cl, cr = cu(x-1), cu(x+1) with cu = fma(u, 2, p).
+__device__ __forceinline__ float jac_bar(float pu, float cl, float cr) {
+  const float h = cl + cr;
+  return __fmul_rn(fmaf(pu, 2.f, h), 1.f / 12.f);
+}
+__device__ __forceinline__ float jac_col(float up, float mid, float dn) { return fmaf(mid, 2.f, up + dn); }
+__device__ __forceinline__ void jac_update(float ub, float vb, float a, float b, float c, float* u, float* v) {
+  const float s = fmaf(a, ub, fmaf(b, vb, c));
+  *u = fmaf(-a, s, ub);
+  *v = fmaf(-b, s, vb);
+}
+
+// One Jacobi sweep, one thread per pixel (reference kernel, global reads).
+__global__ void __launch_bounds__(kThreads) k_hs_jacobi1(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
+                                                         int32_t bpp) {
+  const int64_t pr = blockIdx.x / bpp;
+  const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)g.w * g.h;
+  if (p >= n) return;
+  const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
+  const float* su = uv_buf(c, pr, src_code, g.n0);
+  const float* sv = su + n;
+  const int32_t xl = max(x - 1, 0), xr = min(x + 1, g.w - 1);
+  const int64_t ru = (int64_t)max(y - 1, 0) * g.w, rm = (int64_t)y * g.w, rd = (int64_t)min(y + 1, g.h - 1) * g.w;
+  const float ub = jac_bar(su[ru + x] + su[rd + x], jac_col(su[ru + xl], su[rm + xl], su[rd + xl]),
+                           jac_col(su[ru + xr], su[rm + xr], su[rd + xr]));
+  const float vb = jac_bar(sv[ru + x] + sv[rd + x], jac_col(sv[ru + xl], sv[rm + xl], sv[rd + xl]),
+                           jac_col(sv[ru + xr], sv[rm + xr], sv[rd + xr]));
+  float un, vn;
+  jac_update(ub, vb, plane(c, pr, kPlaneA, g.n0)[p], plane(c, pr, kPlaneB, g.n0)[p], plane(c, pr, kPlaneC, g.n0)[p],
+             &un, &vn);
+  float* du = uv_buf(c, pr, dst_code, g.n0);
+  du[p] = un;
+  du[n + p] = vn;
+}
+
+LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
+  LevelGeom g;
+  g.w = grp.dims[l].w;
+  g.h = grp.dims[l].h;
+  g.has_coarse = (l + 1 < (int32_t)grp.dims.size()) ? 1 : 0;
+  g.cw = g.has_coarse ? grp.dims[l + 1].w : 0;
+  g.ch = g.has_coarse ? grp.dims[l + 1].h : 0;
+  g.n0 = (int64_t)grp.w * grp.h;
+  g.lvl_off = (int64_t)grp.lvl_off[l];
+  g.level = l;
+  return g;
+}
+
+}  // namespace
+
+scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, hipStream_t s) {
+  scn_status st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s);
+  if (st != SCN_OK) return st;
+  uint8_t* base = (uint8_t*)ws;
+  const float alpha2 = prm.alpha * prm.alpha;
+  const int32_t L = plan.levels;
+  for (const FlowGroup& grp : plan.groups) {
+    for (const FlowChunk& ch : grp.chunks) {
+      ChunkPtrs c;
+      c.frames = (const FrameDesc*)(base + ch.frames_off);
+      c.pairs = (const PairDesc*)(base + ch.pairs_off);
+      c.pyr = (float*)(base + plan.scratch_off);
+      c.pyr_floats = (int64_t)grp.pyr_floats;
+      c.scratch = (float*)(base + plan.scratch_off + align_up((size_t)ch.n_frames * grp.pyr_floats * sizeof(float)));
+      c.pair_floats = (int64_t)grp.pair_floats;
+      c.n_pairs = ch.n_pairs;
+      c.n_frames = ch.n_frames;
+      // pyramids of every frame slot of the chunk
+      for (int32_t l = 1; l < L; ++l) {
+        const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
+        const int64_t bpf = ((int64_t)dg.w * dg.h + kThreads - 1) / kThreads;
+        const int64_t grid = bpf * ch.n_frames;
+        if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+        KernelTimer timer("pyr_down", s);
+        hipLaunchKernelGGL(k_pyr_down, dim3((unsigned)grid), dim3(kThreads), 0, s, c, sg, dg, (int32_t)bpf);
+        SCN_LAUNCHED("pyramid launch");
+      }
+      int32_t result = -1;  // buffer code holding the coarser level's flow
+      for (int32_t l = L - 1; l >= 0; --l) {
+        const LevelGeom g = level_geom(grp, l);
+        const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
+        const int64_t grid = bpp * ch.n_pairs;
+        if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+        const int32_t coarse = result < 0 ? 0 : result;
+        const int32_t x = result < 0 ? 0 : 1 - result;
+        {
+          KernelTimer timer("hs_warp", s);
+          hipLaunchKernelGGL(k_hs_warp, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, (int32_t)bpp);
+        }
+        SCN_LAUNCHED("warp launch");
+        const int32_t start_dst = (l == 0 && prm.iters == 0) ? 2 : x;
+        {
+          KernelTimer timer("hs_coef", s);
+          hipLaunchKernelGGL(k_hs_coef, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, start_dst, alpha2,
+                           (int32_t)bpp);
+        }
+        SCN_LAUNCHED("coef launch");
+        int32_t cur = start_dst;
+        for (int32_t it = 0; it < prm.iters; ++it) {
+          const int32_t dst = (l == 0 && it == prm.iters - 1) ? 2 : 1 - cur;
+          {
+            KernelTimer timer("hs_jacobi", s);
+            hipLaunchKernelGGL(k_hs_jacobi1, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, cur, dst, (int32_t)bpp);
+          }
+          SCN_LAUNCHED("jacobi launch");
+          cur = dst;
+        }
+        result = cur;
+      }
+    }
+  }
+  return SCN_OK;
+}
+
+}  // namespace scn

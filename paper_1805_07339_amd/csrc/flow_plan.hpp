@@ -1,0 +1,61 @@
+// Host planning of a batched Horn-Schunck FLOW call: pair lists, per-frame
+// pyramid slots (each sampled frame's pyramid is built once and shared by
+// the pairs that use it -- Sec. 4.2 of the Scanner paper computes only the
+// required elements, once), grouping by resolution, chunking to the
+// workspace, and the device descriptor tables.  No HIP dependency.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace scn {
+
+// Device-visible descriptors (uploaded into the workspace's plan region).
+struct FrameDesc {
+  const uint8_t* y;  // level-0 luma plane (device)
+  int64_t pitch;     // bytes per luma row
+};
+struct PairDesc {
+  int32_t f1, f2;    // frame slots (within the chunk)
+  float* out;        // [2][H][W] output (device)
+};
+
+struct FlowChunk {
+  int64_t n_frames = 0, n_pairs = 0;
+  size_t frames_off = 0, pairs_off = 0;  // offsets of the descriptor arrays in the plan region
+};
+
+struct FlowGroup {
+  int32_t w = 0, h = 0;
+  std::vector<LevelDim> dims;      // per level
+  std::vector<size_t> lvl_off;     // float offset of level l (l >= 1) inside one frame's pyramid slot
+  size_t pyr_floats = 0;           // floats per frame pyramid slot (levels 1..L-1)
+  size_t pair_floats = 0;          // floats per pair scratch (8 planes of level-0 size)
+  int64_t total_pairs = 0;
+  std::vector<FlowChunk> chunks;
+};
+
+struct FlowPlan {
+  std::vector<uint8_t> plan_bytes;  // uploaded to ws[0 .. plan_bytes.size())
+  size_t scratch_off = 0;           // start of the reused scratch region in ws
+  size_t ws_needed = 0;             // bytes for the fastest schedule (one chunk per group)
+  size_t ws_min = 0;                // smallest workable workspace
+  int64_t total_pairs = 0;
+  int32_t levels = 0;
+  std::vector<FlowGroup> groups;
+};
+
+// Per-pair scratch planes (each of level-0 size): coefficient planes a, b, c,
+// the warped second image, and two (u, v) ping-pong buffers.
+enum : int32_t { kPlaneA = 0, kPlaneB = 1, kPlaneC = 2, kPlaneW = 3, kPlaneU0 = 4, kPlaneV0 = 5, kPlaneU1 = 6,
+                 kPlaneV1 = 7, kPairPlanes = 8 };
+
+// Build the plan.  flow may be NULL (sizing only).  ws_bytes = 0 plans one
+// chunk per group (that plan's scratch size is ws_needed); otherwise pairs
+// are chunked so that scratch fits in ws_bytes.
+scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p, float* const* flow,
+                           size_t ws_bytes, FlowPlan* plan);
+
+}  // namespace scn

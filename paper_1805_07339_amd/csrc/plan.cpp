@@ -1,0 +1,144 @@
+#include "plan.hpp"
+
+#include <limits>
+
+namespace scn {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+scn_status check_table(const scn_table* t) {
+  if (!t) { set_error("table is NULL"); return SCN_EINVAL; }
+  if (t->n_frames < 0) { set_error("table n_frames < 0"); return SCN_EINVAL; }
+  if (t->width < 2 || t->height < 2) { set_error("table width/height must be >= 2"); return SCN_EINVAL; }
+  if ((t->width & 1) || (t->height & 1)) {
+    set_error("NV12 width and height must be even");
+    return SCN_EUNSUPPORTED;
+  }
+  if (t->pitch < t->width) { set_error("table pitch < width"); return SCN_EINVAL; }
+  const int64_t need = (int64_t)t->pitch * (t->height + t->height / 2);
+  if (t->frame_bytes < need) { set_error("table frame_bytes < pitch * height * 3/2"); return SCN_EINVAL; }
+  if (t->n_frames > 0 && !t->frames) { set_error("table frames pointer is NULL"); return SCN_EINVAL; }
+  if (t->width > (1 << 15) || t->height > (1 << 15)) {
+    set_error("frame dimensions above 32768 are not supported");
+    return SCN_EUNSUPPORTED;
+  }
+  return SCN_OK;
+}
+
+scn_status resolve(const scn_job* job, std::vector<Slice>* out) {
+  out->clear();
+  if (!job || !job->sampling) { set_error("job or sampling is NULL"); return SCN_EINVAL; }
+  scn_status st = check_table(job->table);
+  if (st != SCN_OK) return st;
+  const scn_sampling& s = *job->sampling;
+  const int64_t n = job->table->n_frames;
+  switch (s.kind) {
+    case SCN_STRIDE: {
+      if (s.step < 1) { set_error("stride step must be >= 1"); return SCN_EINVAL; }
+      if (s.start < 0 || s.stop > n || s.start > s.stop) {
+        set_error("stride needs 0 <= start <= stop <= n_frames");
+        return SCN_EINVAL;
+      }
+      Slice sl;
+      for (int64_t r = s.start; r < s.stop; r += s.step) sl.rows.push_back(r);
+      out->push_back(std::move(sl));
+      return SCN_OK;
+    }
+    case SCN_GATHER: {
+      if (s.n < 0 || (s.n > 0 && !s.idx)) { set_error("gather list is NULL or n < 0"); return SCN_EINVAL; }
+      Slice sl;
+      sl.rows.reserve((size_t)s.n);
+      for (int64_t i = 0; i < s.n; ++i) {
+        const int64_t r = s.idx[i];
+        if (r < 0 || r >= n) { set_error("gather row out of range"); return SCN_EINVAL; }
+        if (i > 0 && r <= s.idx[i - 1]) { set_error("gather rows must be strictly increasing"); return SCN_EINVAL; }
+        sl.rows.push_back(r);
+      }
+      out->push_back(std::move(sl));
+      return SCN_OK;
+    }
+    case SCN_RANGE: {
+      if (s.n < 0 || (s.n > 0 && !s.idx)) { set_error("range list is NULL or n < 0"); return SCN_EINVAL; }
+      int64_t prev_end = 0;
+      for (int64_t i = 0; i < s.n; ++i) {
+        const int64_t b = s.idx[2 * i], e = s.idx[2 * i + 1];
+        if (b < prev_end || e < b || b < 0 || e > n) {
+          set_error("ranges must be half-open, ascending, disjoint and within the table");
+          return SCN_EINVAL;
+        }
+        Slice sl;
+        for (int64_t r = b; r < e; ++r) sl.rows.push_back(r);
+        out->push_back(std::move(sl));
+        prev_end = e;
+      }
+      return SCN_OK;
+    }
+    default:
+      set_error("unknown sampling kind");
+      return SCN_EINVAL;
+  }
+}
+
+scn_status resolve_flat(const scn_job* job, Resolved* out) {
+  std::vector<Slice> sl;
+  scn_status st = resolve(job, &sl);
+  if (st != SCN_OK) return st;
+  out->rows.clear();
+  out->pairs.clear();
+  out->pair_slots.clear();
+  for (const Slice& s : sl) {
+    const int32_t base = (int32_t)out->rows.size();
+    for (size_t i = 0; i < s.rows.size(); ++i) {
+      out->rows.push_back(s.rows[i]);
+      if (i + 1 < s.rows.size()) {
+        out->pairs.emplace_back(s.rows[i], s.rows[i + 1]);
+        out->pair_slots.emplace_back(base + (int32_t)i, base + (int32_t)i + 1);
+      }
+    }
+  }
+  if (out->rows.size() > (size_t)std::numeric_limits<int32_t>::max()) {
+    set_error("too many sampled rows");
+    return SCN_EUNSUPPORTED;
+  }
+  return SCN_OK;
+}
+
+std::vector<LevelDim> level_dims(int32_t w, int32_t h, int32_t levels) {
+  std::vector<LevelDim> d;
+  d.push_back({w, h});
+  for (int32_t l = 1; l < levels; ++l) {
+    const LevelDim& p = d.back();
+    d.push_back({(p.w + 1) / 2, (p.h + 1) / 2});
+  }
+  return d;
+}
+
+scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
+  if (!p) { set_error("flow params are NULL"); return SCN_EINVAL; }
+  if (p->levels < 1 || p->levels > 12) { set_error("levels must be in [1, 12]"); return SCN_EINVAL; }
+  if (!(p->alpha > 0.0f) || p->alpha > 1e6f) { set_error("alpha must be in (0, 1e6]"); return SCN_EINVAL; }
+  if (p->iters < 0 || p->iters > 100000) { set_error("iters must be in [0, 100000]"); return SCN_EINVAL; }
+  if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > 16) {
+    set_error("sweeps_per_pass must be in [0, 16]");
+    return SCN_EINVAL;
+  }
+  if (p->tile_rows < 0 || p->tile_rows > 16) { set_error("tile_rows must be in [0, 16]"); return SCN_EINVAL; }
+  if (t) {
+    auto d = level_dims(t->width, t->height, p->levels);
+    if (d.back().w < 2 || d.back().h < 2) {
+      set_error("coarsest pyramid level would be smaller than 2x2");
+      return SCN_EUNSUPPORTED;
+    }
+  }
+  return SCN_OK;
+}
+
+size_t hist_ws_bytes(int64_t m) { return align_up((size_t)m * sizeof(int64_t)) + kAlign; }
+
+}  // namespace scn

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol scn.h declares, and its planning/validation entry points return
+the documented counts and error codes (validation happens before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+import paper_1805_07339_amd as scn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "scn.h")).read()
+    return sorted(set(re.findall(r"\b(scn_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = scn.lib()
+    declared = header_symbols()
+    assert set(declared) == set(scn.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _cpu_table(n_frames=100, w=64, h=48, pitch=None):
+    pitch = w if pitch is None else pitch
+    fb = pitch * h * 3 // 2
+    t = torch.zeros((n_frames, fb), dtype=torch.uint8)
+    return scn.Table.from_tensor(t, w, h, pitch)
+
+
+def test_counts_stride_gather_range():
+    t = _cpu_table(2400)
+    assert scn.count_rows(scn.Job(t, scn.Sampling.stride(24, 0, 2400))) == 100
+    assert scn.count_pairs(scn.Job(t, scn.Sampling.stride(24, 0, 2400))) == 99
+    assert scn.count_pairs(scn.Job(t, scn.Sampling.gather([1, 5, 9]))) == 2
+    j = scn.Job(t, scn.Sampling.range([(10, 14), (20, 23)]))
+    assert scn.count_rows(j) == 7 and scn.count_pairs(j) == 5
+    assert scn.count_pairs(scn.Job(t, scn.Sampling.stride(1, 5, 5))) == 0
+
+
+@pytest.mark.parametrize("samp", [
+    scn.Sampling.stride(0, 0, 10),
+    scn.Sampling.stride(1, 0, 2401),
+    scn.Sampling.gather([3, 3]),
+    scn.Sampling.gather([2400]),
+    scn.Sampling.range([(5, 3)]),
+    scn.Sampling.range([(0, 5), (4, 8)]),
+])
+def test_invalid_sampling_is_rejected(samp):
+    t = _cpu_table(2400)
+    n = scn.lib().scn_count_rows(ctypes.byref(scn.Job(t, samp).cjob))
+    assert n == scn.SCN_EINVAL
+    assert scn.lib().scn_last_error().decode() != ""
+
+
+def test_odd_size_unsupported_and_bad_table_invalid():
+    t = _cpu_table(4, 63, 48)
+    assert scn.lib().scn_count_rows(ctypes.byref(scn.Job(t, scn.Sampling.stride(1, 0, 4)).cjob)) == scn.SCN_EUNSUPPORTED
+    t2 = _cpu_table(4, 64, 48)
+    t2.frame_bytes = 10
+    assert scn.lib().scn_count_rows(ctypes.byref(scn.Job(t2, scn.Sampling.stride(1, 0, 4)).cjob)) == scn.SCN_EINVAL
+
+
+def test_hist_validation_before_any_device_work():
+    t = _cpu_table(8)
+    job = scn.Job(t, scn.Sampling.stride(1, 0, 8))
+    need = scn.workspace_bytes(scn.SCN_OP_HIST, [job])
+    assert need >= 8 * 8
+    L = scn.lib()
+    out = torch.zeros(8 * 48, dtype=torch.int32)
+    ws = torch.zeros(need, dtype=torch.uint8)
+    # workspace too small -> SCN_ENOSPACE, nothing enqueued
+    assert L.scn_hist(ctypes.byref(job.cjob), out.data_ptr(), ws.data_ptr(), need - 1, None) == scn.SCN_ENOSPACE
+    assert L.scn_hist(ctypes.byref(job.cjob), None, ws.data_ptr(), need, None) == scn.SCN_EINVAL
+    assert L.scn_sample_convert(ctypes.byref(job.cjob), 64, 48, 7, out.data_ptr(), ws.data_ptr(), need,
+                                None) == scn.SCN_EINVAL
+    # empty sampling: OK with no work and no pointers needed
+    empty = scn.Job(t, scn.Sampling.gather([]))
+    assert L.scn_hist(ctypes.byref(empty.cjob), None, None, 0, None) == scn.SCN_OK
+
+
+def test_flow_workspace_and_param_validation():
+    t = _cpu_table(100, 64, 48)
+    job = scn.Job(t, scn.Sampling.stride(10, 0, 100))
+    p = scn.flow_params(levels=3)
+    need = scn.workspace_bytes(scn.SCN_OP_FLOW, [job], p)
+    # 9 pairs x 8 planes of 64x48 floats + 10 pyramids (levels 1, 2) + plan region
+    assert need >= 9 * 8 * 64 * 48 * 4 + 10 * (32 * 24 + 16 * 12) * 4
+    L = scn.lib()
+    bad = scn.flow_params(levels=7)  # 64x48 -> 2x2 at the 6th level, 1x1 at the 7th
+    assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, scn._jobs_array([job]), 1, ctypes.byref(bad)) == 0
+    bad2 = scn.flow_params(alpha=0.0)
+    assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, scn._jobs_array([job]), 1, ctypes.byref(bad2)) == 0
+    out = torch.zeros(9 * 2 * 64 * 48, dtype=torch.float32)
+    ptrs = (ctypes.c_void_p * 1)(out.data_ptr())
+    ws = torch.zeros(1024, dtype=torch.uint8)
+    assert L.scn_flow(scn._jobs_array([job]), 1, ctypes.byref(p), ptrs, ws.data_ptr(), 1024,
+                      None) == scn.SCN_ENOSPACE
+    nul = (ctypes.c_void_p * 1)(None)
+    assert L.scn_flow(scn._jobs_array([job]), 1, ctypes.byref(p), nul, ws.data_ptr(), need, None) == scn.SCN_EINVAL
+
+
+def test_flow_uneven_jobs_workspace_grows_with_pairs():
+    a = scn.Job(_cpu_table(50, 64, 48), scn.Sampling.stride(1, 0, 10))
+    b = scn.Job(_cpu_table(50, 128, 96), scn.Sampling.range([(0, 5), (20, 30)]))
+    p = scn.flow_params(levels=3)
+    na = scn.workspace_bytes(scn.SCN_OP_FLOW, [a], p)
+    nab = scn.workspace_bytes(scn.SCN_OP_FLOW, [a, b], p)
+    assert nab > na
