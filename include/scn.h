@@ -97,15 +97,19 @@ typedef struct {
  * `levels` >= 1 pyramid levels (each level halves the size, rounding up;
  * the coarsest level must be at least 2x2), smoothness weight `alpha` > 0 in
  * luma code units, `iters` >= 0 Jacobi iterations at every level.
- * `sweeps_per_pass` (0 = autotuned) and `tile_rows` (0 = autotuned) select
- * the Jacobi kernel's temporal blocking and tile height; every choice gives
- * bitwise identical results. */
+ * `sweeps_per_pass` and `tile_variant` select the Jacobi schedule: 0 and 0
+ * let the library's autotuner choose (tuned once per level shape, see
+ * SCN_TUNE_CACHE / SCN_TUNE in the implementation notes); sweeps_per_pass = 1
+ * with tile_variant = 0 runs one sweep per launch; otherwise sweeps_per_pass
+ * sweeps (1..63) run per launch on register tiles of variant 1..4 (128 x 128,
+ * 128 x 128, 128 x 64, 128 x 64 pixels).  Every schedule gives bitwise
+ * identical results. */
 typedef struct {
   int32_t levels;
   float alpha;
   int32_t iters;
   int32_t sweeps_per_pass;
-  int32_t tile_rows;
+  int32_t tile_variant;
   int32_t reserved;
 } scn_flow_params;
 

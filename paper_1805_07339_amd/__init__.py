@@ -51,7 +51,7 @@ class CJob(ctypes.Structure):
 
 class CFlowParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("alpha", ctypes.c_float), ("iters", ctypes.c_int32),
-                ("sweeps_per_pass", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sweeps_per_pass", ctypes.c_int32), ("tile_variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
@@ -195,8 +195,8 @@ def _jobs_array(jobs: Sequence[Job]):
 
 
 def flow_params(levels: int = 4, alpha: float = 10.0, iters: int = 50, sweeps_per_pass: int = 0,
-                tile_rows: int = 0) -> CFlowParams:
-    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_rows, 0)
+                tile_variant: int = 0) -> CFlowParams:
+    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_variant, 0)
 
 
 def count_rows(job: Job) -> int:

@@ -22,6 +22,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "flow_plan.hpp"
@@ -248,6 +255,125 @@ __global__ void __launch_bounds__(kThreads) k_hs_jacobi1(ChunkPtrs c, LevelGeom 
   du[n + p] = vn;
 }
 
+// ---------------------------------------------------------------------------
+// Temporally blocked Jacobi: `ns` sweeps per launch on a register tile.
+//
+// A workgroup of NW waves owns a tile of 128 columns x NW*R rows: lane l of
+// wave w holds columns ox + 2l, ox + 2l + 1 of rows oy + w*R .. + R-1 (u, v
+// and the coefficients a, b, c, all in VGPRs).  Horizontal neighbours of the
+// two columns come from the adjacent lane through DPP wave shifts folded
+// into the adds; vertical neighbours are the thread's own rows, and the rows
+// across a wave boundary go through a small double-buffered LDS exchange
+// (one barrier per sweep).  The tile carries a halo of `halo` >= ns pixels on
+// every side, loaded with mirrored (half-sample symmetric) coordinates:
+// reflecting u, v and the coefficients at the image border makes every
+// mirrored pixel evolve exactly like its mirror image (the sums are single
+// commutative adds), which is the clamp-to-edge neighbourhood of the
+// reference iteration, bitwise.  Each sweep invalidates one more ring of the
+// halo; after ns sweeps the interior (128 - 2 halo) x (NW*R - 2 halo) pixels
+// equal ns sweeps of the one-sweep kernel and are stored.
+__device__ __forceinline__ int32_t reflect(int32_t c, int32_t n) {
+  c = (c < 0) ? -1 - c : c;
+  c = (c >= n) ? 2 * n - 1 - c : c;
+  return min(max(c, 0), n - 1);
+}
+__device__ __forceinline__ float dpp_from_left(float x) {   // lane l receives lane l-1
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float x) {  // lane l receives lane l+1
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
+}
+
+template <int R, int NW>
+__global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
+                                                          int32_t ns, int32_t halo, int32_t tiles_x,
+                                                          int32_t tiles_per_pair) {
+  constexpr int TH = NW * R;
+  __shared__ float4 xch[2][NW][2][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t pr = blockIdx.x / tiles_per_pair;
+  const int32_t t = blockIdx.x % tiles_per_pair;
+  const int32_t ty = t / tiles_x, tx = t % tiles_x;
+  const int32_t ox = tx * (128 - 2 * halo) - halo;
+  const int32_t oy = ty * (TH - 2 * halo) - halo;
+  const int64_t n = (int64_t)g.w * g.h;
+  const float* su = uv_buf(c, pr, src_code, g.n0);
+  const float* sv = su + n;
+  const float* pa = plane(c, pr, kPlaneA, g.n0);
+  const float* pb = plane(c, pr, kPlaneB, g.n0);
+  const float* pc = plane(c, pr, kPlaneC, g.n0);
+  const int32_t cx0 = ox + 2 * lane, cx1 = cx0 + 1;
+  const int32_t gx0 = reflect(cx0, g.w), gx1 = reflect(cx1, g.w);
+
+  float u[2][R], v[2][R], A[2][R], B[2][R], C[2][R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t row = (int64_t)reflect(oy + w * R + r, g.h) * g.w;
+    u[0][r] = su[row + gx0];
+    u[1][r] = su[row + gx1];
+    v[0][r] = sv[row + gx0];
+    v[1][r] = sv[row + gx1];
+    A[0][r] = pa[row + gx0];
+    A[1][r] = pa[row + gx1];
+    B[0][r] = pb[row + gx0];
+    B[1][r] = pb[row + gx1];
+    C[0][r] = pc[row + gx0];
+    C[1][r] = pc[row + gx1];
+  }
+
+  for (int s = 0; s < ns; ++s) {
+    const int slot = s & 1;
+    xch[slot][w][0][lane] = make_float4(u[0][0], u[1][0], v[0][0], v[1][0]);
+    xch[slot][w][1][lane] = make_float4(u[0][R - 1], u[1][R - 1], v[0][R - 1], v[1][R - 1]);
+    __syncthreads();
+    const float4 up = (w > 0) ? xch[slot][w - 1][1][lane] : xch[slot][w][0][lane];
+    const float4 dn = (w < NW - 1) ? xch[slot][w + 1][0][lane] : xch[slot][w][1][lane];
+    float pu0 = up.x, pu1 = up.y, pv0 = up.z, pv1 = up.w;  // old values of the row above
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float nu0 = (r + 1 < R) ? u[0][r + 1] : dn.x;
+      const float nu1 = (r + 1 < R) ? u[1][r + 1] : dn.y;
+      const float nv0 = (r + 1 < R) ? v[0][r + 1] : dn.z;
+      const float nv1 = (r + 1 < R) ? v[1][r + 1] : dn.w;
+      // vertical pair sums and [1 2 1] columns
+      const float qu0 = pu0 + nu0, qu1 = pu1 + nu1, qv0 = pv0 + nv0, qv1 = pv1 + nv1;
+      const float cu0 = fmaf(u[0][r], 2.f, qu0), cu1 = fmaf(u[1][r], 2.f, qu1);
+      const float cv0 = fmaf(v[0][r], 2.f, qv0), cv1 = fmaf(v[1][r], 2.f, qv1);
+      // horizontal: column 0's left is the left lane's column 1; column 1's right is the right lane's column 0
+      const float ub0 = jac_bar(qu0, dpp_from_left(cu1), cu1);
+      const float ub1 = jac_bar(qu1, cu0, dpp_from_right(cu0));
+      const float vb0 = jac_bar(qv0, dpp_from_left(cv1), cv1);
+      const float vb1 = jac_bar(qv1, cv0, dpp_from_right(cv0));
+      pu0 = u[0][r];
+      pu1 = u[1][r];
+      pv0 = v[0][r];
+      pv1 = v[1][r];
+      jac_update(ub0, vb0, A[0][r], B[0][r], C[0][r], &u[0][r], &v[0][r]);
+      jac_update(ub1, vb1, A[1][r], B[1][r], C[1][r], &u[1][r], &v[1][r]);
+    }
+  }
+
+  float* du = uv_buf(c, pr, dst_code, g.n0);
+  float* dv = du + n;
+  const bool in0 = (cx0 >= ox + halo) && (cx0 < ox + 128 - halo) && (cx0 < g.w);
+  const bool in1 = (cx1 >= ox + halo) && (cx1 < ox + 128 - halo) && (cx1 < g.w);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int32_t yy = oy + w * R + r;
+    if (yy < oy + halo || yy >= oy + TH - halo || yy >= g.h) continue;
+    const int64_t row = (int64_t)yy * g.w;
+    if (in0) {
+      du[row + cx0] = u[0][r];
+      dv[row + cx0] = v[0][r];
+    }
+    if (in1) {
+      du[row + cx1] = u[1][r];
+      dv[row + cx1] = v[1][r];
+    }
+  }
+}
+
 LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
   LevelGeom g;
   g.w = grp.dims[l].w;
@@ -262,6 +388,67 @@ LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
 }
 
 }  // namespace
+
+// Jacobi kernel variants: (rows per wave, waves per workgroup); variant 0 is
+// the one-sweep reference kernel.
+struct JacobiVariant {
+  int32_t rows, waves;
+};
+constexpr JacobiVariant kVariants[] = {{1, 4}, {8, 16}, {16, 8}, {8, 8}, {4, 16}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+struct JacobiChoice {
+  int32_t variant;  // index into kVariants
+  int32_t k;        // sweeps per pass (= halo)
+};
+
+bool variant_fits(int v, int32_t k, const LevelGeom& g) {
+  if (v == 0) return k == 1;
+  const int32_t th = kVariants[v].rows * kVariants[v].waves;
+  return k >= 1 && 2 * k < 128 && 2 * k < th && k <= g.w && k <= g.h;
+}
+
+scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const LevelGeom& g, int64_t n_pairs,
+                         int32_t src, int32_t dst, int32_t ns, hipStream_t s) {
+  KernelTimer timer("hs_jacobi", s);
+  if (jc.variant == 0) {
+    const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
+    for (int32_t it = 0; it < ns; ++it) {
+      const int32_t d = (it == ns - 1) ? dst : (it % 2 == 0 ? 1 - src : src);
+      const int32_t sc = (it == 0) ? src : (it % 2 == 1 ? 1 - src : src);
+      hipLaunchKernelGGL(k_hs_jacobi1, dim3((unsigned)(bpp * n_pairs)), dim3(kThreads), 0, s, c, g, sc, d,
+                         (int32_t)bpp);
+    }
+    SCN_LAUNCHED("jacobi launch");
+    return SCN_OK;
+  }
+  const JacobiVariant v = kVariants[jc.variant];
+  const int32_t th = v.rows * v.waves;
+  const int32_t tiles_x = (g.w + (128 - 2 * jc.k) - 1) / (128 - 2 * jc.k);
+  const int32_t tiles_y = (g.h + (th - 2 * jc.k) - 1) / (th - 2 * jc.k);
+  const int64_t tpp = (int64_t)tiles_x * tiles_y;
+  const int64_t grid = tpp * n_pairs;
+  if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+  const dim3 gd((unsigned)grid), bd(64 * v.waves);
+  switch (jc.variant) {
+    case 1: hipLaunchKernelGGL((k_hs_jacobi_tb<8, 16>), gd, bd, 0, s, c, g, src, dst, ns, jc.k, tiles_x, (int32_t)tpp); break;
+    case 2: hipLaunchKernelGGL((k_hs_jacobi_tb<16, 8>), gd, bd, 0, s, c, g, src, dst, ns, jc.k, tiles_x, (int32_t)tpp); break;
+    case 3: hipLaunchKernelGGL((k_hs_jacobi_tb<8, 8>), gd, bd, 0, s, c, g, src, dst, ns, jc.k, tiles_x, (int32_t)tpp); break;
+    case 4: hipLaunchKernelGGL((k_hs_jacobi_tb<4, 16>), gd, bd, 0, s, c, g, src, dst, ns, jc.k, tiles_x, (int32_t)tpp); break;
+    default: set_error("internal: bad Jacobi variant"); return SCN_EINVAL;
+  }
+  SCN_LAUNCHED("jacobi launch");
+  return SCN_OK;
+}
+
+// Default schedule without tuning: 10 sweeps per pass on 128 x 128 tiles.
+JacobiChoice default_choice(const LevelGeom& g, int32_t iters) {
+  for (int32_t k : {10, 8, 5, 4, 3, 2})
+    if (k <= iters && variant_fits(1, k, g)) return JacobiChoice{1, k};
+  return JacobiChoice{0, 1};
+}
+
+#include "tune.inc"
 
 scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, hipStream_t s) {
   scn_status st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s);
@@ -311,14 +498,16 @@ scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, 
         }
         SCN_LAUNCHED("coef launch");
         int32_t cur = start_dst;
-        for (int32_t it = 0; it < prm.iters; ++it) {
-          const int32_t dst = (l == 0 && it == prm.iters - 1) ? 2 : 1 - cur;
-          {
-            KernelTimer timer("hs_jacobi", s);
-            hipLaunchKernelGGL(k_hs_jacobi1, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, cur, dst, (int32_t)bpp);
+        if (prm.iters > 0) {
+          const JacobiChoice jc = choose_jacobi(grp, l, ch.n_pairs, prm, c, g, cur, s);
+          for (int32_t done = 0; done < prm.iters;) {
+            const int32_t ns = std::min(jc.k, prm.iters - done);
+            const int32_t dst = (l == 0 && done + ns == prm.iters) ? 2 : 1 - cur;
+            st = launch_jacobi(jc, c, g, ch.n_pairs, cur, dst, ns, s);
+            if (st != SCN_OK) return st;
+            cur = dst;
+            done += ns;
           }
-          SCN_LAUNCHED("jacobi launch");
-          cur = dst;
         }
         result = cur;
       }

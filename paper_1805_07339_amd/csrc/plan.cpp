@@ -124,11 +124,11 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
   if (p->levels < 1 || p->levels > 12) { set_error("levels must be in [1, 12]"); return SCN_EINVAL; }
   if (!(p->alpha > 0.0f) || p->alpha > 1e6f) { set_error("alpha must be in (0, 1e6]"); return SCN_EINVAL; }
   if (p->iters < 0 || p->iters > 100000) { set_error("iters must be in [0, 100000]"); return SCN_EINVAL; }
-  if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > 16) {
-    set_error("sweeps_per_pass must be in [0, 16]");
+  if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > 63) {
+    set_error("sweeps_per_pass must be in [0, 63]");
     return SCN_EINVAL;
   }
-  if (p->tile_rows < 0 || p->tile_rows > 16) { set_error("tile_rows must be in [0, 16]"); return SCN_EINVAL; }
+  if (p->tile_variant < 0 || p->tile_variant > 4) { set_error("tile_variant must be in [0, 4]"); return SCN_EINVAL; }
   if (t) {
     auto d = level_dims(t->width, t->height, p->levels);
     if (d.back().w < 2 || d.back().h < 2) {

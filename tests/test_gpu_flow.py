@@ -128,3 +128,23 @@ def test_flow_c2_1080p_sampled_pairs():
         d = _maxdiff(f[k].cpu().numpy(), exp)
         print("C2 pair %d max |d| = %.3g" % (k, d))
         assert d <= TOL
+
+
+@pytest.mark.parametrize("w,h,levels", [(320, 240, 3), (250, 186, 4), (130, 34, 2)])
+def test_jacobi_schedules_are_bitwise_identical(w, h, levels):
+    """Every Jacobi schedule (one sweep per launch, or k sweeps per launch on
+    each register-tile variant, or the autotuned choice) gives the same bits."""
+    need_gpu()
+    frames, _ = c1_frames(n=3, w=w, h=h, seed=7 + w)
+    tab = table_from_frames(frames, 3, [0, 1, 2], w, h)
+    job = scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.stride(1, 0, 3))
+    (ref,) = scn.flow([job], scn.flow_params(levels=levels, sweeps_per_pass=1))
+    ref = ref.clone()
+    exp = _oracle_pairs(tab, [(0, 1), (1, 2)], w, h, w, levels)
+    assert _maxdiff(ref.cpu().numpy(), exp) <= TOL
+    for variant in (1, 2, 3, 4):
+        for k in (2, 5, 8, 13):
+            (f,) = scn.flow([job], scn.flow_params(levels=levels, sweeps_per_pass=k, tile_variant=variant))
+            assert torch.equal(f, ref), (variant, k)
+    (f,) = scn.flow([job], scn.flow_params(levels=levels))
+    assert torch.equal(f, ref)
