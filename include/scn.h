@@ -114,7 +114,14 @@ typedef struct {
 } scn_flow_params;
 
 enum { SCN_RGB24 = 0, SCN_GRAY8 = 1 };
-enum { SCN_OP_CONVERT = 0, SCN_OP_HIST = 1, SCN_OP_FLOW = 2, SCN_OP_SURROGATE = 3 };
+enum {
+  SCN_OP_CONVERT = 0,
+  SCN_OP_HIST = 1,
+  SCN_OP_FLOW = 2,
+  SCN_OP_SURROGATE = 3,        /* scn_flow_surrogate (p = fallback parameters) */
+  SCN_OP_SURROGATE_GRADS = 4,  /* scn_surrogate_grads */
+  SCN_OP_SURROGATE_INFER = 5   /* scn_surrogate_infer */
+};
 
 /* Number of sampled rows M of a job, or a negative scn_status. */
 int64_t scn_count_rows(const scn_job* job);
@@ -123,9 +130,12 @@ int64_t scn_count_rows(const scn_job* job);
  * slice; Sec. 3.2 stencil after sampling), or a negative scn_status. */
 int64_t scn_count_pairs(const scn_job* job);
 
-/* Minimum workspace for an operation (SCN_OP_*) over `n_jobs` jobs; for
- * SCN_OP_CONVERT and SCN_OP_HIST n_jobs must be 1.  Returns 0 on invalid
- * arguments (see scn_last_error). */
+/* Workspace for an operation (SCN_OP_*) over `n_jobs` jobs: the size for
+ * the fastest schedule (SCN_OP_FLOW and SCN_OP_SURROGATE also run in smaller
+ * workspaces, down to a minimum, by processing pairs in chunks).  For
+ * SCN_OP_CONVERT and SCN_OP_HIST n_jobs must be 1; p is the flow (or
+ * fallback) parameters where needed.  Returns 0 on invalid arguments (see
+ * scn_last_error). */
 size_t scn_workspace_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p);
 
 /* Gather the sampled rows of one job and convert them from NV12 to RGB24
@@ -155,13 +165,67 @@ scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_byte
 scn_status scn_flow(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p,
                     float* const* flow, void* ws, size_t ws_bytes, scn_stream_t stream);
 
+/* ---- learned flow surrogate ---------------------------------------------
+ * A learned model run as a graph operation (Sec. 3.1, Sec. 5.1.2 DNN) used
+ * as a cheap FLOW with a conditional fallback to the full computation, the
+ * pattern of the hyperlapse application's conditional matching
+ * (Sec. 5.2.2).  Network: 3x3 convolutions conv1 2->32, conv2 32->64 stride
+ * 2, conv3 64->96 stride 2, x2 nearest upsampling + conv4 96->64, x2 + conv5
+ * 64->32, conv6 32->2; ReLU after conv1..conv5; BF16 weights and
+ * activations, FP32 accumulation and bias.  Input: per pair, the 2x2 mean of
+ * each frame's luma (round half up) as (v - 128)/64 (half resolution; frame
+ * width and height must be multiples of 8, else SCN_EUNSUPPORTED).  Output:
+ * half-resolution flow, upsampled x2 bilinearly (half-pixel centres) and
+ * scaled by 2 to full-resolution pixels.
+ * Parameters: scn_net_params() FP32 values, per layer the weights
+ * [c_out][c_in][3][3] then the bias [c_out], conv1 first ("master" vector).
+ * The network blob (scn_net_bytes() bytes, device, 256-byte aligned) holds
+ * the BF16 weights in the kernels' layouts and the FP32 biases. */
+size_t scn_net_bytes(void);
+int32_t scn_net_params(void);
+
+/* Convert FP32 master parameters (device) into a network blob (device). */
+scn_status scn_net_pack(const float* master, void* net, scn_stream_t stream);
+
+/* One Adam step (bias-corrected; `step` counts from 1) on the FP32 master
+ * parameters with moment buffers m, v (device, scn_net_params() floats
+ * each, zero before the first step) and gradients `grads`; also repacks the
+ * updated parameters into `net`. */
+scn_status scn_adam_step(float* master, float* m, float* v, const float* grads, int32_t step, float lr,
+                         float beta1, float beta2, float eps, void* net, scn_stream_t stream);
+
+/* Loss and gradients of one training batch: every pair of the jobs (one
+ * resolution) is a sample; the loss is the mean over samples and
+ * full-resolution pixels of sqrt(du^2 + dv^2 + 0.01^2) between the network's
+ * full-resolution flow and targets[j] (device, [P_j][2][H][W], e.g. scn_flow's
+ * output).  grads: device, scn_net_params() floats (overwritten); loss: device, 1 float. */
+scn_status scn_surrogate_grads(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* targets,
+                               float* grads, float* loss, void* ws, size_t ws_bytes, scn_stream_t stream);
+
+/* The network's full-resolution flow for every pair (no gate, no fallback).
+ * flow[j]: device, float [P_j][2][H][W]. */
+scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* flow, void* ws,
+                               size_t ws_bytes, scn_stream_t stream);
+
+/* FLOW with the surrogate and a residual gate: per pair the network's flow w
+ * is kept if r = mean over pixels of |Y2(x + w) - Y1(x)| (luma, clamped
+ * bilinear warp) is <= gate_tau, else the pair is recomputed by scn_flow's
+ * plain Horn-Schunck solver with fallback_p.  The decision is taken on the
+ * device (no host synchronisation).  flow[j]: device [P_j][2][H][W];
+ * fell_back[j] (device, uint8 [P_j], may be NULL) receives 1 for recomputed
+ * pairs; residual[j] (device, float [P_j], may be NULL) receives r. */
+scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* fallback_p, const void* net,
+                              float gate_tau, float* const* flow, uint8_t* const* fell_back, float* const* residual,
+                              void* ws, size_t ws_bytes, scn_stream_t stream);
+
 /* Kernel timing for diagnostics and benchmarks.  scn_timing_enable(1, n)
  * creates a pool of 2n HIP events; while enabled, every kernel launch of the
  * library is bracketed by two events recorded on its stream (at most n
  * launches until the next scn_timing_reset).  scn_timing_read synchronises
  * those events and returns the summed duration and launch count of one
  * kernel class ("hist16", "nv12_rgb24", "nv12_resize", "luma_copy",
- * "pyr_down", "hs_warp", "hs_coef", "hs_jacobi"); it returns SCN_ENOSPACE if
+ * "pyr_down", "hs_warp", "hs_coef", "hs_jacobi", "conv_fwd", "conv_dx",
+ * "conv_dw", "flow_up", "gate"); it returns SCN_ENOSPACE if
  * launches were dropped because the pool was full.  Not thread-safe with
  * respect to concurrent enable/reset. */
 scn_status scn_timing_enable(int32_t enable, int32_t max_launches);

@@ -22,6 +22,7 @@ SCN_OK, SCN_EINVAL, SCN_EUNSUPPORTED, SCN_ENOSPACE, SCN_EHIP = 0, -1, -2, -3, -4
 SCN_STRIDE, SCN_GATHER, SCN_RANGE = 0, 1, 2
 SCN_RGB24, SCN_GRAY8 = 0, 1
 SCN_OP_CONVERT, SCN_OP_HIST, SCN_OP_FLOW, SCN_OP_SURROGATE = 0, 1, 2, 3
+SCN_OP_SURROGATE_GRADS, SCN_OP_SURROGATE_INFER = 4, 5
 
 _STATUS_NAMES = {SCN_EINVAL: "SCN_EINVAL", SCN_EUNSUPPORTED: "SCN_EUNSUPPORTED", SCN_ENOSPACE: "SCN_ENOSPACE",
                  SCN_EHIP: "SCN_EHIP"}
@@ -57,7 +58,8 @@ class CFlowParams(ctypes.Structure):
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
            "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
-           "scn_timing_reset", "scn_timing_read"]
+           "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
+           "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate"]
 
 _lib = None
 
@@ -98,6 +100,22 @@ def lib() -> ctypes.CDLL:
     L.scn_timing_reset.restype = ctypes.c_int
     L.scn_timing_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]
     L.scn_timing_read.restype = ctypes.c_int
+    L.scn_net_bytes.argtypes = []
+    L.scn_net_bytes.restype = ctypes.c_size_t
+    L.scn_net_params.argtypes = []
+    L.scn_net_params.restype = ctypes.c_int32
+    L.scn_net_pack.argtypes = [vp, vp, vp]
+    L.scn_net_pack.restype = ctypes.c_int
+    L.scn_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, vp, vp]
+    L.scn_adam_step.restype = ctypes.c_int
+    L.scn_surrogate_grads.argtypes = [P(CJob), ctypes.c_int32, vp, P(vp), vp, vp, vp, ctypes.c_size_t, vp]
+    L.scn_surrogate_grads.restype = ctypes.c_int
+    L.scn_surrogate_infer.argtypes = [P(CJob), ctypes.c_int32, vp, P(vp), vp, ctypes.c_size_t, vp]
+    L.scn_surrogate_infer.restype = ctypes.c_int
+    L.scn_flow_surrogate.argtypes = [P(CJob), ctypes.c_int32, P(CFlowParams), vp, ctypes.c_float, P(vp), P(vp), P(vp),
+                                     vp, ctypes.c_size_t, vp]
+    L.scn_flow_surrogate.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -307,6 +325,86 @@ def flow(jobs: Sequence[Job], params: Optional[CFlowParams] = None, outs: Option
     nbytes = ws.numel() if ws_bytes is None else min(ws_bytes, ws.numel())
     _check(lib().scn_flow(arr, len(jobs), ctypes.byref(params), ptrs, ws.data_ptr(), nbytes, _stream(stream)))
     return outs
+
+
+# ---------------------------------------------------------------------------
+# learned surrogate
+
+
+def net_params() -> int:
+    return int(lib().scn_net_params())
+
+
+def net_bytes() -> int:
+    return int(lib().scn_net_bytes())
+
+
+def net_pack(master: torch.Tensor, net: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """FP32 master parameters (device, [net_params()]) -> network blob (uint8 device tensor)."""
+    if net is None:
+        net = torch.empty(net_bytes(), dtype=torch.uint8, device=master.device)
+    _check(lib().scn_net_pack(master.data_ptr(), net.data_ptr(), _stream(stream)))
+    return net
+
+
+def adam_step(master, m, v, grads, step: int, lr: float, net, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().scn_adam_step(master.data_ptr(), m.data_ptr(), v.data_ptr(), grads.data_ptr(), step, lr, beta1, beta2,
+                               eps, net.data_ptr(), _stream(stream)))
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() if (t is not None and t.numel()) else None for t in ts])
+
+
+def surrogate_grads(jobs: Sequence[Job], net: torch.Tensor, targets: List[torch.Tensor],
+                    grads: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None, stream=None,
+                    ws: Optional[torch.Tensor] = None):
+    dev = net.device
+    if grads is None:
+        grads = torch.empty(net_params(), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = _ws(dev, workspace_bytes(SCN_OP_SURROGATE_GRADS, jobs), "surrogate")
+    _check(lib().scn_surrogate_grads(_jobs_array(jobs), len(jobs), net.data_ptr(), _ptr_array(targets),
+                                     grads.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return grads, loss
+
+
+def surrogate_infer(jobs: Sequence[Job], net: torch.Tensor, outs: Optional[List[torch.Tensor]] = None, stream=None,
+                    ws: Optional[torch.Tensor] = None) -> List[torch.Tensor]:
+    if outs is None:
+        outs = [torch.empty((count_pairs(j), 2, j.table.height, j.table.width), dtype=torch.float32,
+                            device=net.device) for j in jobs]
+    if ws is None:
+        ws = _ws(net.device, workspace_bytes(SCN_OP_SURROGATE_INFER, jobs), "surrogate")
+    _check(lib().scn_surrogate_infer(_jobs_array(jobs), len(jobs), net.data_ptr(), _ptr_array(outs), ws.data_ptr(),
+                                     ws.numel(), _stream(stream)))
+    return outs
+
+
+def flow_surrogate(jobs: Sequence[Job], net: torch.Tensor, tau: float, params: Optional[CFlowParams] = None,
+                   outs=None, fell_back=None, residual=None, stream=None, ws: Optional[torch.Tensor] = None,
+                   ws_bytes: Optional[int] = None):
+    """Surrogate flow with the residual gate and the plain-solver fallback.
+    Returns (flows, fell_back flags, residuals), one entry per job."""
+    params = flow_params() if params is None else params
+    dev = net.device
+    if outs is None:
+        outs = [torch.empty((count_pairs(j), 2, j.table.height, j.table.width), dtype=torch.float32, device=dev)
+                for j in jobs]
+    if fell_back is None:
+        fell_back = [torch.empty(count_pairs(j), dtype=torch.uint8, device=dev) for j in jobs]
+    if residual is None:
+        residual = [torch.empty(count_pairs(j), dtype=torch.float32, device=dev) for j in jobs]
+    if ws is None:
+        need = workspace_bytes(SCN_OP_SURROGATE, jobs, params) if ws_bytes is None else ws_bytes
+        ws = _ws(dev, need, "surrogate")
+    nbytes = ws.numel() if ws_bytes is None else min(ws_bytes, ws.numel())
+    _check(lib().scn_flow_surrogate(_jobs_array(jobs), len(jobs), ctypes.byref(params), net.data_ptr(), tau,
+                                    _ptr_array(outs), _ptr_array(fell_back), _ptr_array(residual), ws.data_ptr(),
+                                    nbytes, _stream(stream)))
+    return outs, fell_back, residual
 
 
 def timing_enable(on: bool = True, max_launches: int = 65536):

@@ -11,6 +11,7 @@ scn_status launch_hist(const scn_table& t, const int64_t* rows_dev, int64_t m, u
 scn_status launch_convert(const scn_table& t, const int64_t* rows_dev, int64_t m, int32_t out_w, int32_t out_h,
                           int32_t fmt, uint8_t* out, hipStream_t s);
 scn_status run_flow(const FlowPlan& plan, const scn_flow_params& p, void* ws, hipStream_t s);
+size_t surrogate_ws_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p);
 }  // namespace scn
 
 using namespace scn;
@@ -57,6 +58,8 @@ size_t scn_workspace_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, cons
     if (build_flow_plan(jobs, n_jobs, p, nullptr, /*ws_bytes=*/0, &plan) != SCN_OK) return 0;
     return plan.ws_needed;
   }
+  if (op == SCN_OP_SURROGATE || op == SCN_OP_SURROGATE_GRADS || op == SCN_OP_SURROGATE_INFER)
+    return surrogate_ws_bytes(op, jobs, n_jobs, p);
   set_error("unknown op");
   return 0;
 }

@@ -56,6 +56,8 @@ struct ChunkPtrs {
   float* scratch;        // pair scratch, pair_floats each
   int64_t pair_floats;
   int64_t n_pairs, n_frames;
+  const uint8_t* active;   // per pair: compute this pair (NULL: all pairs)
+  const uint8_t* factive;  // per frame: some active pair uses it (NULL: all frames)
 };
 
 // (u, v) buffer codes: 0 and 1 are the pair's ping-pong buffers, 2 is the output.
@@ -138,6 +140,7 @@ __global__ void __launch_bounds__(kThreads) k_pyr_down(ChunkPtrs c, LevelGeom sr
   const int64_t f = blockIdx.x / bpf;
   const int64_t p = (int64_t)(blockIdx.x % bpf) * kThreads + threadIdx.x;
   if (p >= (int64_t)dst.w * dst.h) return;
+  if (c.factive && !c.factive[f]) return;
   const int32_t x = (int32_t)(p % dst.w), y = (int32_t)(p / dst.w);
   const Img im = level_img(c, (int32_t)f, src);
   const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
@@ -172,6 +175,7 @@ __global__ void __launch_bounds__(kThreads) k_hs_warp(ChunkPtrs c, LevelGeom g, 
   const int64_t pr = blockIdx.x / bpp;
   const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
   if (p >= (int64_t)g.w * g.h) return;
+  if (c.active && !c.active[pr]) return;
   const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
   float u0 = 0.f, v0 = 0.f;
   if (g.has_coarse) {
@@ -190,6 +194,7 @@ __global__ void __launch_bounds__(kThreads) k_hs_coef(ChunkPtrs c, LevelGeom g, 
   const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
   const int64_t n = (int64_t)g.w * g.h;
   if (p >= n) return;
+  if (c.active && !c.active[pr]) return;
   const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
   float u0 = 0.f, v0 = 0.f;
   if (g.has_coarse) {
@@ -238,6 +243,7 @@ __global__ void __launch_bounds__(kThreads) k_hs_jacobi1(ChunkPtrs c, LevelGeom 
   const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
   const int64_t n = (int64_t)g.w * g.h;
   if (p >= n) return;
+  if (c.active && !c.active[pr]) return;
   const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
   const float* su = uv_buf(c, pr, src_code, g.n0);
   const float* sv = su + n;
@@ -293,6 +299,7 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int64_t pr = blockIdx.x / tiles_per_pair;
+  if (c.active && !c.active[pr]) return;  // uniform over the workgroup, before any barrier
   const int32_t t = blockIdx.x % tiles_per_pair;
   const int32_t ty = t / tiles_x, tx = t % tiles_x;
   const int32_t ox = tx * (128 - 2 * halo) - halo;
@@ -450,69 +457,80 @@ JacobiChoice default_choice(const LevelGeom& g, int32_t iters) {
 
 #include "tune.inc"
 
-scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, hipStream_t s) {
-  scn_status st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s);
-  if (st != SCN_OK) return st;
+// Flow of one chunk of pairs (pyramids, then coarse-to-fine warp, coef and
+// Jacobi).  `active` / `factive` (device, per pair / per frame slot) restrict
+// the work to a subset of the chunk's pairs (NULL: all).
+scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
+                          const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
+                          hipStream_t s) {
   uint8_t* base = (uint8_t*)ws;
   const float alpha2 = prm.alpha * prm.alpha;
   const int32_t L = plan.levels;
-  for (const FlowGroup& grp : plan.groups) {
-    for (const FlowChunk& ch : grp.chunks) {
-      ChunkPtrs c;
-      c.frames = (const FrameDesc*)(base + ch.frames_off);
-      c.pairs = (const PairDesc*)(base + ch.pairs_off);
-      c.pyr = (float*)(base + plan.scratch_off);
-      c.pyr_floats = (int64_t)grp.pyr_floats;
-      c.scratch = (float*)(base + plan.scratch_off + align_up((size_t)ch.n_frames * grp.pyr_floats * sizeof(float)));
-      c.pair_floats = (int64_t)grp.pair_floats;
-      c.n_pairs = ch.n_pairs;
-      c.n_frames = ch.n_frames;
-      // pyramids of every frame slot of the chunk
-      for (int32_t l = 1; l < L; ++l) {
-        const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
-        const int64_t bpf = ((int64_t)dg.w * dg.h + kThreads - 1) / kThreads;
-        const int64_t grid = bpf * ch.n_frames;
-        if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
-        KernelTimer timer("pyr_down", s);
-        hipLaunchKernelGGL(k_pyr_down, dim3((unsigned)grid), dim3(kThreads), 0, s, c, sg, dg, (int32_t)bpf);
-        SCN_LAUNCHED("pyramid launch");
-      }
-      int32_t result = -1;  // buffer code holding the coarser level's flow
-      for (int32_t l = L - 1; l >= 0; --l) {
-        const LevelGeom g = level_geom(grp, l);
-        const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
-        const int64_t grid = bpp * ch.n_pairs;
-        if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
-        const int32_t coarse = result < 0 ? 0 : result;
-        const int32_t x = result < 0 ? 0 : 1 - result;
-        {
-          KernelTimer timer("hs_warp", s);
-          hipLaunchKernelGGL(k_hs_warp, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, (int32_t)bpp);
-        }
-        SCN_LAUNCHED("warp launch");
-        const int32_t start_dst = (l == 0 && prm.iters == 0) ? 2 : x;
-        {
-          KernelTimer timer("hs_coef", s);
-          hipLaunchKernelGGL(k_hs_coef, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, start_dst, alpha2,
-                           (int32_t)bpp);
-        }
-        SCN_LAUNCHED("coef launch");
-        int32_t cur = start_dst;
-        if (prm.iters > 0) {
-          const JacobiChoice jc = choose_jacobi(grp, l, ch.n_pairs, prm, c, g, cur, s);
-          for (int32_t done = 0; done < prm.iters;) {
-            const int32_t ns = std::min(jc.k, prm.iters - done);
-            const int32_t dst = (l == 0 && done + ns == prm.iters) ? 2 : 1 - cur;
-            st = launch_jacobi(jc, c, g, ch.n_pairs, cur, dst, ns, s);
-            if (st != SCN_OK) return st;
-            cur = dst;
-            done += ns;
-          }
-        }
-        result = cur;
+  scn_status st;
+  ChunkPtrs c;
+  c.frames = (const FrameDesc*)(base + ch.frames_off);
+  c.pairs = (const PairDesc*)(base + ch.pairs_off);
+  c.pyr = (float*)(base + plan.scratch_off);
+  c.pyr_floats = (int64_t)grp.pyr_floats;
+  c.scratch = (float*)(base + plan.scratch_off + chunk_pyr_bytes(grp, ch));
+  c.pair_floats = (int64_t)grp.pair_floats;
+  c.n_pairs = ch.n_pairs;
+  c.n_frames = ch.n_frames;
+  c.active = active;
+  c.factive = factive;
+  // pyramids of every frame slot of the chunk
+  for (int32_t l = 1; l < L; ++l) {
+    const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
+    const int64_t bpf = ((int64_t)dg.w * dg.h + kThreads - 1) / kThreads;
+    const int64_t grid = bpf * ch.n_frames;
+    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    KernelTimer timer("pyr_down", s);
+    hipLaunchKernelGGL(k_pyr_down, dim3((unsigned)grid), dim3(kThreads), 0, s, c, sg, dg, (int32_t)bpf);
+    SCN_LAUNCHED("pyramid launch");
+  }
+  int32_t result = -1;  // buffer code holding the coarser level's flow
+  for (int32_t l = L - 1; l >= 0; --l) {
+    const LevelGeom g = level_geom(grp, l);
+    const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
+    const int64_t grid = bpp * ch.n_pairs;
+    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    const int32_t coarse = result < 0 ? 0 : result;
+    const int32_t x = result < 0 ? 0 : 1 - result;
+    {
+      KernelTimer timer("hs_warp", s);
+      hipLaunchKernelGGL(k_hs_warp, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, (int32_t)bpp);
+    }
+    SCN_LAUNCHED("warp launch");
+    const int32_t start_dst = (l == 0 && prm.iters == 0) ? 2 : x;
+    {
+      KernelTimer timer("hs_coef", s);
+      hipLaunchKernelGGL(k_hs_coef, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, start_dst, alpha2,
+                         (int32_t)bpp);
+    }
+    SCN_LAUNCHED("coef launch");
+    int32_t cur = start_dst;
+    if (prm.iters > 0) {
+      const JacobiChoice jc = choose_jacobi(grp, l, ch.n_pairs, prm, c, g, cur, s);
+      for (int32_t done = 0; done < prm.iters;) {
+        const int32_t ns = std::min(jc.k, prm.iters - done);
+        const int32_t dst = (l == 0 && done + ns == prm.iters) ? 2 : 1 - cur;
+        st = launch_jacobi(jc, c, g, ch.n_pairs, cur, dst, ns, s);
+        if (st != SCN_OK) return st;
+        cur = dst;
+        done += ns;
       }
     }
+    result = cur;
   }
+  return SCN_OK;
+}
+
+scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, hipStream_t s) {
+  scn_status st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s);
+  if (st != SCN_OK) return st;
+  for (const FlowGroup& grp : plan.groups)
+    for (const FlowChunk& ch : grp.chunks)
+      if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, s)) != SCN_OK) return st;
   return SCN_OK;
 }
 

@@ -12,17 +12,27 @@ struct PairRef {
   int32_t job;
   int64_t r1, r2;
   float* out;
+  uint8_t* fb;
+  float* resid;
 };
 
 size_t chunk_scratch(const FlowGroup& g, int64_t frames, int64_t pairs) {
   return align_up((size_t)frames * g.pyr_floats * sizeof(float)) +
-         align_up((size_t)pairs * g.pair_floats * sizeof(float));
+         align_up((size_t)pairs * g.pair_floats * sizeof(float)) + align_up((size_t)pairs * g.extra_pair_bytes);
 }
 
 }  // namespace
 
+size_t chunk_pyr_bytes(const FlowGroup& g, const FlowChunk& c) {
+  return align_up((size_t)c.n_frames * g.pyr_floats * sizeof(float));
+}
+size_t chunk_pairs_bytes(const FlowGroup& g, const FlowChunk& c) {
+  return align_up((size_t)c.n_pairs * g.pair_floats * sizeof(float));
+}
+
 scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p, float* const* flow,
-                           size_t ws_bytes, FlowPlan* plan) {
+                           size_t ws_bytes, FlowPlan* plan, ExtraPairBytes extra, uint8_t* const* fell_back,
+                           float* const* residual) {
   *plan = FlowPlan();
   if (!jobs || n_jobs < 1) { set_error("jobs is NULL or n_jobs < 1"); return SCN_EINVAL; }
   scn_status st = check_flow_params(p, nullptr);
@@ -58,6 +68,7 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
       }
       g.pyr_floats = off;
       g.pair_floats = (size_t)kPairPlanes * t.width * t.height;
+      g.extra_pair_bytes = extra ? extra(t.width, t.height) : 0;
       plan->groups.push_back(g);
       gpairs.emplace_back();
     } else {
@@ -65,13 +76,15 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
     }
     const size_t fsz = (size_t)2 * t.width * t.height;
     for (size_t k = 0; k < r.pairs.size(); ++k)
-      gpairs[gi].push_back(PairRef{j, r.pairs[k].first, r.pairs[k].second, flow ? flow[j] + k * fsz : nullptr});
+      gpairs[gi].push_back(PairRef{j, r.pairs[k].first, r.pairs[k].second, flow ? flow[j] + k * fsz : nullptr,
+                                   (fell_back && fell_back[j]) ? fell_back[j] + k : nullptr,
+                                   (residual && residual[j]) ? residual[j] + k : nullptr});
   }
 
   int64_t total = 0;
   for (auto& v : gpairs) total += (int64_t)v.size();
   plan->total_pairs = total;
-  const size_t plan_reserved = align_up(48 * (size_t)total + 256);
+  const size_t plan_reserved = align_up((2 * sizeof(FrameDesc) + sizeof(PairDesc)) * (size_t)total + 256);
   plan->scratch_off = plan_reserved;
   size_t need = 0, min_need = 0;
   for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
@@ -120,6 +133,8 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
         d.f1 = get(k1, pr.r1);
         d.f2 = get(k2, pr.r2);
         d.out = pr.out;
+        d.fb = pr.fb;
+        d.resid = pr.resid;
         pds.push_back(d);
         ++i;
       }

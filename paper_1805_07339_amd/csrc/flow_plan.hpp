@@ -19,7 +19,9 @@ struct FrameDesc {
 };
 struct PairDesc {
   int32_t f1, f2;    // frame slots (within the chunk)
-  float* out;        // [2][H][W] output (device)
+  float* out;        // [2][H][W] output (device); the training target for gradient calls
+  uint8_t* fb;       // surrogate path: fell-back flag of this pair (device, may be NULL)
+  float* resid;      // surrogate path: gate residual of this pair (device, may be NULL)
 };
 
 struct FlowChunk {
@@ -33,6 +35,7 @@ struct FlowGroup {
   std::vector<size_t> lvl_off;     // float offset of level l (l >= 1) inside one frame's pyramid slot
   size_t pyr_floats = 0;           // floats per frame pyramid slot (levels 1..L-1)
   size_t pair_floats = 0;          // floats per pair scratch (8 planes of level-0 size)
+  size_t extra_pair_bytes = 0;     // additional per-pair scratch (surrogate path)
   int64_t total_pairs = 0;
   std::vector<FlowChunk> chunks;
 };
@@ -55,7 +58,15 @@ enum : int32_t { kPlaneA = 0, kPlaneB = 1, kPlaneC = 2, kPlaneW = 3, kPlaneU0 = 
 // Build the plan.  flow may be NULL (sizing only).  ws_bytes = 0 plans one
 // chunk per group (that plan's scratch size is ws_needed); otherwise pairs
 // are chunked so that scratch fits in ws_bytes.
+// extra_pair_bytes(w, h) adds per-pair scratch for the surrogate path (NULL:
+// none); fell_back / residual are optional per-job surrogate outputs.
+typedef size_t (*ExtraPairBytes)(int32_t w, int32_t h);
 scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p, float* const* flow,
-                           size_t ws_bytes, FlowPlan* plan);
+                           size_t ws_bytes, FlowPlan* plan, ExtraPairBytes extra = nullptr,
+                           uint8_t* const* fell_back = nullptr, float* const* residual = nullptr);
+
+// Scratch layout of one chunk (offsets from the start of the scratch region).
+size_t chunk_pyr_bytes(const FlowGroup& g, const FlowChunk& c);
+size_t chunk_pairs_bytes(const FlowGroup& g, const FlowChunk& c);
 
 }  // namespace scn

@@ -1,0 +1,1056 @@
+// Learned flow surrogate for gfx950: BF16 MFMA implicit-GEMM convolutions
+// (forward, input gradient, weight gradient), network input, flow
+// upsampling, Charbonnier loss with its adjoint, Adam, and the residual
+// gate.  Layouts and the MFMA lane mapping are described in
+// surrogate_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "flow_plan.hpp"
+#include "surrogate_kernels.hpp"
+
+namespace scn {
+namespace sg {
+
+namespace {
+
+struct CGeom {
+  int32_t n;        // images (pairs) in the batch
+  int32_t hi, wi;   // stored input size
+  int32_t he, we;   // effective input size (2x the stored size for upsampled inputs)
+  int32_t ho, wo;   // output size
+};
+
+__device__ __forceinline__ bf16x8 ld8(const bf16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ __forceinline__ bf16x8 zero8() {
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  return __builtin_bit_cast(bf16x8, z);
+}
+__device__ __forceinline__ bf16x8 pack8(const bf16_t (&v)[8]) {
+  uint4 u;
+  u.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+  u.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+  u.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+  u.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// forward: y[m][co] = act(bias[co] + sum_{tap, ci} W[tap][co][ci] x_e(m, tap)[ci])
+// One wave computes 16*MR output pixels x all output channels.
+template <int L, int MR>
+__global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
+                                                  void* __restrict__ y, CGeom g) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16;
+  constexpr bool UP = D.up != 0, RELU = D.relu != 0;
+  const bf16_t* wf = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
+  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t M = (int64_t)g.n * g.ho * g.wo;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wv) * (16 * MR);
+  int pn[MR], poy[MR], pox[MR];
+  bool pv[MR];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr) {
+    const int64_t m = base + mr * 16 + r16;
+    pv[mr] = m < M;
+    const int64_t mm = pv[mr] ? m : 0;
+    pox[mr] = (int)(mm % g.wo);
+    const int64_t t = mm / g.wo;
+    poy[mr] = (int)(t % g.ho);
+    pn[mr] = (int)(t / g.ho);
+  }
+  f32x4 acc[MR][NB];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if constexpr (CI == 2) {
+    // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3.
+    bf16x8 a[MR];
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr) {
+      bf16_t v[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int tap = 4 * kg + j;
+        uint32_t pair = 0;
+        if (tap < 9) {
+          const int iy = poy[mr] * S + tap / 3 - 1, ix = pox[mr] * S + tap % 3 - 1;
+          if (pv[mr] && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
+            const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+            pair = *reinterpret_cast<const uint32_t*>(x + (((int64_t)pn[mr] * g.hi + sy) * g.wi + sx) * 2);
+          }
+        }
+        v[2 * j] = (bf16_t)(pair & 0xFFFFu);
+        v[2 * j + 1] = (bf16_t)(pair >> 16);
+      }
+      a[mr] = pack8(v);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 b = ld8(wf + (nb * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+    }
+  } else {
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      int64_t off[MR];
+      bool ok[MR];
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        const int iy = poy[mr] * S + ky - 1, ix = pox[mr] * S + kx - 1;
+        ok[mr] = pv[mr] && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we;
+        const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+        off[mr] = ok[mr] ? (((int64_t)pn[mr] * g.hi + sy) * g.wi + sx) * CI : 0;
+      }
+#pragma unroll
+      for (int cb = 0; cb < CI / 32; ++cb) {
+        bf16x8 a[MR];
+#pragma unroll
+        for (int mr = 0; mr < MR; ++mr) a[mr] = ok[mr] ? ld8(x + off[mr] + cb * 32 + kg * 8) : zero8();
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8 b = ld8(wf + ((int64_t)(tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8));
+#pragma unroll
+          for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = nb * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = base + mr * 16 + kg * 4 + i;
+        if (m >= M || co >= CO) continue;
+        float v = acc[mr][nb][i] + bias[co];
+        if (RELU) v = fmaxf(v, 0.f);
+        if constexpr (L == kLayers - 1)
+          reinterpret_cast<float*>(y)[m * CO + co] = v;
+        else
+          reinterpret_cast<bf16_t*>(y)[m * CO + co] = f2bf(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// input gradient of the effective input: dxe[m][ci] = sum_{tap, co} W[tap][co][ci] dy(out(m, tap))[co]
+template <int L, int MR>
+__global__ void __launch_bounds__(256) k_conv_dx(const void* __restrict__ dy, const uint8_t* __restrict__ blob,
+                                                 float* __restrict__ dxe, CGeom g) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, NB = CI / 16;
+  static_assert(CI % 16 == 0, "input-gradient kernel needs ci % 16 == 0");
+  const bf16_t* wt = reinterpret_cast<const bf16_t*>(blob + blob_tr_off(L));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t M = (int64_t)g.n * g.he * g.we;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wv) * (16 * MR);
+  int pn[MR], piy[MR], pix[MR];
+  bool pv[MR];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr) {
+    const int64_t m = base + mr * 16 + r16;
+    pv[mr] = m < M;
+    const int64_t mm = pv[mr] ? m : 0;
+    pix[mr] = (int)(mm % g.we);
+    const int64_t t = mm / g.we;
+    piy[mr] = (int)(t % g.he);
+    pn[mr] = (int)(t / g.he);
+  }
+  f32x4 acc[MR][NB];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto out_of = [&](int iv, int k, int n_out, int* o) -> bool {
+    const int num = iv + 1 - k;
+    if (num < 0) return false;
+    if (S == 2) {
+      if (num & 1) return false;
+      *o = num >> 1;
+    } else {
+      *o = num;
+    }
+    return *o < n_out;
+  };
+  if constexpr (CO == 2) {
+    // K = 18 (9 taps x 2 output channels) in one block of 32; dy is FP32 [m][2].
+    const float* dyf = reinterpret_cast<const float*>(dy);
+    bf16x8 a[MR];
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr) {
+      bf16_t v[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int tap = 4 * kg + j;
+        float d0 = 0.f, d1 = 0.f;
+        int oy, ox;
+        if (tap < 9 && pv[mr] && out_of(piy[mr], tap / 3, g.ho, &oy) && out_of(pix[mr], tap % 3, g.wo, &ox)) {
+          const float2 d = *reinterpret_cast<const float2*>(dyf + (((int64_t)pn[mr] * g.ho + oy) * g.wo + ox) * 2);
+          d0 = d.x;
+          d1 = d.y;
+        }
+        v[2 * j] = f2bf(d0);
+        v[2 * j + 1] = f2bf(d1);
+      }
+      a[mr] = pack8(v);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 b = ld8(wt + (nb * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+    }
+  } else {
+    const bf16_t* dyb = reinterpret_cast<const bf16_t*>(dy);
+    for (int tap = 0; tap < 9; ++tap) {
+      int64_t off[MR];
+      bool ok[MR];
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        int oy = 0, ox = 0;
+        ok[mr] = pv[mr] && out_of(piy[mr], tap / 3, g.ho, &oy) && out_of(pix[mr], tap % 3, g.wo, &ox);
+        off[mr] = ok[mr] ? (((int64_t)pn[mr] * g.ho + oy) * g.wo + ox) * CO : 0;
+      }
+#pragma unroll
+      for (int cb = 0; cb < CO / 32; ++cb) {
+        bf16x8 a[MR];
+#pragma unroll
+        for (int mr = 0; mr < MR; ++mr) a[mr] = ok[mr] ? ld8(dyb + off[mr] + cb * 32 + kg * 8) : zero8();
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8 b = ld8(wt + ((int64_t)(tap * CI + nb * 16 + r16) * CO + cb * 32 + kg * 8));
+#pragma unroll
+          for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = base + mr * 16 + kg * 4 + i;
+        if (m < M) dxe[m * CI + nb * 16 + r16] = acc[mr][nb][i];
+      }
+}
+
+// previous layer's output gradient: adjoint of the x2 upsampling (if any),
+// times the ReLU derivative of the stored activation, rounded to BF16.
+__global__ void k_dx_post(const float* __restrict__ dxe, const bf16_t* __restrict__ act, bf16_t* __restrict__ gout,
+                          int64_t n_elems, int32_t h, int32_t w, int32_t c, int32_t up) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_elems) return;
+  float v;
+  if (up) {
+    const int32_t ch = (int32_t)(i % c);
+    const int64_t p = i / c;
+    const int32_t xx = (int32_t)(p % w);
+    const int64_t t = p / w;
+    const int32_t yy = (int32_t)(t % h);
+    const int64_t n = t / h;
+    const int64_t W2 = 2 * (int64_t)w, H2 = 2 * (int64_t)h;
+    const int64_t b = ((n * H2 + 2 * yy) * W2 + 2 * xx) * c + ch;
+    v = (dxe[b] + dxe[b + c]) + (dxe[b + W2 * c] + dxe[b + W2 * c + c]);
+  } else {
+    v = dxe[i];
+  }
+  gout[i] = bf2f(act[i]) > 0.f ? f2bf(v) : (bf16_t)0;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient, split over pixel chunks (deterministic):
+//   part[chunk][tap][co][ci] = sum_{m in chunk} dy[m][co] x_e(m, tap)[ci]
+//   partb[chunk][co] = sum_{m in chunk} dy[m][co]  (tap-0 workgroups)
+// Each step stages 32 pixels of dy and of the tap's input, transposed to
+// [channel][pixel] in LDS, so that 8 consecutive pixels of one channel are a
+// 16-byte MFMA fragment.
+template <int L>
+__global__ void __launch_bounds__(256) k_conv_dw(const void* __restrict__ dy, const bf16_t* __restrict__ x,
+                                                 float* __restrict__ part, float* __restrict__ partb, CGeom g,
+                                                 int32_t chunk_px) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), CIP = cpad(CI);
+  constexpr bool UP = D.up != 0;
+  constexpr int TCO = COP / 16, TCI = CIP / 16, NT = TCO * TCI, TPW = (NT + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16_t sdy[COP][40];
+  __shared__ __attribute__((aligned(16))) bf16_t sx[CIP][40];
+  const int tap = blockIdx.x % 9;
+  const int64_t chunk = blockIdx.x / 9;
+  const int ky = tap / 3, kx = tap % 3;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int64_t M = (int64_t)g.n * g.ho * g.wo;
+  const int64_t m0 = chunk * chunk_px, m1 = min(M, m0 + chunk_px);
+  f32x4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  for (int64_t ms = m0; ms < m1; ms += 32) {
+    // stage dy: 32 pixels x COP channels
+    for (int e = tid; e < 32 * COP; e += 256) {
+      const int p = e / COP, c = e % COP;
+      const int64_t m = ms + p;
+      float v = 0.f;
+      if (m < m1 && c < CO) {
+        if constexpr (L == kLayers - 1)
+          v = reinterpret_cast<const float*>(dy)[m * CO + c];
+        else
+          v = bf2f(reinterpret_cast<const bf16_t*>(dy)[m * CO + c]);
+      }
+      sdy[c][p] = f2bf(v);
+    }
+    // stage the tap's input: 32 pixels x CIP channels
+    for (int e = tid; e < 32 * CIP; e += 256) {
+      const int p = e / CIP, c = e % CIP;
+      const int64_t m = ms + p;
+      bf16_t v = 0;
+      if (m < m1 && c < CI) {
+        const int ox = (int)(m % g.wo);
+        const int64_t t = m / g.wo;
+        const int oy = (int)(t % g.ho);
+        const int64_t n = t / g.ho;
+        const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
+        if (iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
+          const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+          v = x[((n * g.hi + sy) * g.wi + sx) * CI + c];
+        }
+      }
+      sx[c][p] = v;
+    }
+    __syncthreads();
+    if (tap == 0 && tid < CO) {
+      for (int p = 0; p < 32; ++p) bsum += bf2f(sdy[tid][p]);
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wv + 4 * t;
+      if (tile < NT) {
+        const int tco = tile / TCI, tci = tile % TCI;
+        const bf16x8 a = ld8(&sdy[tco * 16 + r16][kg * 8]);
+        const bf16x8 b = ld8(&sx[tci * 16 + r16][kg * 8]);
+        acc[t] = mfma(a, b, acc[t]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wv + 4 * t;
+    if (tile >= NT) continue;
+    const int tco = tile / TCI, tci = tile % TCI;
+    const int ci = tci * 16 + r16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = tco * 16 + kg * 4 + i;
+      if (co < CO && ci < CI) part[((chunk * 9 + tap) * CO + co) * CI + ci] = acc[t][i];
+    }
+  }
+  if (tap == 0 && tid < CO) partb[chunk * CO + tid] = bsum;
+}
+
+// Sum the chunk partials in chunk order into the gradient vector (master layout).
+__global__ void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ partb, float* __restrict__ grads,
+                            int64_t chunks, int32_t ci, int32_t co, int32_t w_off, int32_t b_off) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nw = (int64_t)co * ci * 9;
+  if (i < nw) {
+    // master layout [co][ci][ky][kx]
+    const int tap = (int)(i % 9);
+    const int64_t t = i / 9;
+    const int c_in = (int)(t % ci), c_out = (int)(t / ci);
+    float s = 0.f;
+    for (int64_t k = 0; k < chunks; ++k) s += part[((k * 9 + tap) * co + c_out) * ci + c_in];
+    grads[w_off + i] = s;
+  } else if (i < nw + co) {
+    const int c_out = (int)(i - nw);
+    float s = 0.f;
+    for (int64_t k = 0; k < chunks; ++k) s += partb[k * co + c_out];
+    grads[b_off + c_out] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// network input: per pair, 2x2 mean of each frame's luma (round half up) as (v - 128)/64 in BF16.
+__global__ void k_net_input(const FrameDesc* __restrict__ frames, const PairDesc* __restrict__ pairs,
+                            bf16_t* __restrict__ x, int32_t h, int32_t w, int64_t n_pairs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_pairs * h * w) return;
+  const int32_t xx = (int32_t)(i % w);
+  const int64_t t = i / w;
+  const int32_t yy = (int32_t)(t % h);
+  const int64_t p = t / h;
+  bf16_t out[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const FrameDesc fd = frames[f == 0 ? pairs[p].f1 : pairs[p].f2];
+    const uint8_t* r0 = fd.y + (int64_t)(2 * yy) * fd.pitch + 2 * xx;
+    const int s = (int)r0[0] + r0[1] + r0[fd.pitch] + r0[fd.pitch + 1];
+    out[f] = f2bf((float)(((s + 2) >> 2) - 128) * (1.f / 64.f));
+  }
+  *reinterpret_cast<uint32_t*>(x + i * 2) = (uint32_t)out[0] | ((uint32_t)out[1] << 16);
+}
+
+// Bilinear x2 upsampling tap (half-pixel centres, clamped).
+struct UpTap {
+  int i0, i1;
+  float f;
+};
+__device__ __forceinline__ UpTap up_tap(int x, int n_half) {
+  float X = ((float)x + 0.5f) * 0.5f - 0.5f;
+  X = fminf(fmaxf(X, 0.f), (float)(n_half - 1));
+  UpTap t;
+  t.i0 = (int)floorf(X);
+  t.i1 = min(t.i0 + 1, n_half - 1);
+  t.f = X - (float)t.i0;
+  return t;
+}
+
+__device__ __forceinline__ float2 full_flow_at(const float* __restrict__ half, int x, int y, int h, int w) {
+  const UpTap tx = up_tap(x, w), ty = up_tap(y, h);
+  const float2 a = *reinterpret_cast<const float2*>(half + ((int64_t)ty.i0 * w + tx.i0) * 2);
+  const float2 b = *reinterpret_cast<const float2*>(half + ((int64_t)ty.i0 * w + tx.i1) * 2);
+  const float2 c = *reinterpret_cast<const float2*>(half + ((int64_t)ty.i1 * w + tx.i0) * 2);
+  const float2 d = *reinterpret_cast<const float2*>(half + ((int64_t)ty.i1 * w + tx.i1) * 2);
+  const float u = (1.f - ty.f) * ((1.f - tx.f) * a.x + tx.f * b.x) + ty.f * ((1.f - tx.f) * c.x + tx.f * d.x);
+  const float v = (1.f - ty.f) * ((1.f - tx.f) * a.y + tx.f * b.y) + ty.f * ((1.f - tx.f) * c.y + tx.f * d.y);
+  return make_float2(2.f * u, 2.f * v);
+}
+
+// full-resolution flow [2][H][W] per pair from the half-resolution output [h][w][2];
+// pairs whose keep flag is 0 are skipped (their output comes from elsewhere).
+__global__ void k_flow_up(const float* __restrict__ half, const PairDesc* __restrict__ pairs, int32_t h, int32_t w,
+                          int64_t n_pairs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int32_t W = 2 * w, H = 2 * h;
+  if (i >= n_pairs * H * W) return;
+  const int32_t x = (int32_t)(i % W);
+  const int64_t t = i / W;
+  const int32_t y = (int32_t)(t % H);
+  const int64_t p = t / H;
+  const float2 f = full_flow_at(half + p * (int64_t)h * w * 2, x, y, h, w);
+  float* out = pairs[p].out;
+  out[(int64_t)y * W + x] = f.x;
+  out[(int64_t)H * W + (int64_t)y * W + x] = f.y;
+}
+
+// Charbonnier loss against the target flow and its gradient w.r.t. the
+// half-resolution output (adjoint of the x2 upsampling, gathered per half
+// pixel).  Full pixel (x, y) counts its loss term at half pixel (x/2, y/2).
+__global__ void k_loss_grad(const float* __restrict__ half, const PairDesc* __restrict__ pairs,
+                            float* __restrict__ ghalf, float* __restrict__ loss_part, int32_t h, int32_t w,
+                            int64_t n_pairs, float scale) {
+  __shared__ float red[256];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float own = 0.f;
+  if (i < n_pairs * h * w) {
+    const int32_t hx = (int32_t)(i % w);
+    const int64_t t = i / w;
+    const int32_t hy = (int32_t)(t % h);
+    const int64_t p = t / h;
+    const int32_t W = 2 * w, H = 2 * h;
+    const float* hp = half + p * (int64_t)h * w * 2;
+    const float* tg = pairs[p].out;
+    float gu = 0.f, gv = 0.f;
+    for (int y = max(2 * hy - 2, 0); y <= min(2 * hy + 2, H - 1); ++y) {
+      const UpTap ty = up_tap(y, h);
+      const float wy = (ty.i0 == hy ? 1.f - ty.f : 0.f) + (ty.i1 == hy ? ty.f : 0.f);
+      for (int x = max(2 * hx - 2, 0); x <= min(2 * hx + 2, W - 1); ++x) {
+        const UpTap tx = up_tap(x, w);
+        const float wx = (tx.i0 == hx ? 1.f - tx.f : 0.f) + (tx.i1 == hx ? tx.f : 0.f);
+        const bool owned = (x >> 1) == hx && (y >> 1) == hy;
+        if (wx * wy == 0.f && !owned) continue;
+        const float2 f = full_flow_at(hp, x, y, h, w);
+        const float du = f.x - tg[(int64_t)y * W + x];
+        const float dv = f.y - tg[(int64_t)H * W + (int64_t)y * W + x];
+        const float r = sqrtf(du * du + dv * dv + 1e-4f);
+        if (owned) own += r;
+        const float k = 2.f * wx * wy * scale / r;
+        gu += k * du;
+        gv += k * dv;
+      }
+    }
+    ghalf[i * 2] = gu;
+    ghalf[i * 2 + 1] = gv;
+  }
+  red[threadIdx.x] = own;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_loss(const float* __restrict__ part, int64_t n, float scale, float* __restrict__ loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// pack FP32 master weights into the BF16 blob (forward and transposed layouts) + FP32 bias
+__device__ void pack_one(int64_t i, float wv, uint8_t* blob) {
+  for (int l = 0; l < kLayers; ++l) {
+    const int ci = kNet[l].ci, co = kNet[l].co;
+    const int64_t wo = param_w_off(l), bo = param_b_off(l);
+    if (i >= wo && i < bo) {
+      const int64_t j = i - wo;
+      const int tap = (int)(j % 9);
+      const int64_t t = j / 9;
+      const int c_in = (int)(t % ci), c_out = (int)(t / ci);
+      const bf16_t b = f2bf(wv);
+      bf16_t* wf = reinterpret_cast<bf16_t*>(blob + blob_fwd_off(l));
+      bf16_t* wt = reinterpret_cast<bf16_t*>(blob + blob_tr_off(l));
+      if (ci == 2)
+        wf[c_out * 32 + 2 * tap + c_in] = b;
+      else
+        wf[((int64_t)tap * cpad(co) + c_out) * ci + c_in] = b;
+      if (co == 2)
+        wt[c_in * 32 + 2 * tap + c_out] = b;
+      else
+        wt[((int64_t)tap * ci + c_in) * co + c_out] = b;
+      return;
+    }
+    if (i >= bo && i < bo + co) {
+      reinterpret_cast<float*>(blob + blob_bias_off(l))[i - bo] = wv;
+      return;
+    }
+  }
+}
+
+__global__ void k_pack(const float* __restrict__ master, uint8_t* __restrict__ blob) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < kParams) pack_one(i, master[i], blob);
+}
+
+__global__ void k_zero_bytes(uint32_t* __restrict__ p, int64_t n_words) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n_words) p[i] = 0u;
+}
+
+__global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                       uint8_t* __restrict__ blob) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= kParams) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float w = master[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  master[i] = w;
+  pack_one(i, w, blob);
+}
+
+// ---------------------------------------------------------------------------
+// residual gate: per pair, mean |I2(x + w) - I1(x)| over full-resolution luma
+// (clamped bilinear warp), in two deterministic stages.
+__global__ void k_gate_partial(const FrameDesc* __restrict__ frames, const PairDesc* __restrict__ pairs,
+                               float* __restrict__ part, int32_t W, int32_t H, int32_t blocks_per_pair) {
+  __shared__ float red[256];
+  const int64_t p = blockIdx.x / blocks_per_pair;
+  const int64_t px = (int64_t)(blockIdx.x % blocks_per_pair) * 256 + threadIdx.x;
+  float r = 0.f;
+  if (px < (int64_t)W * H) {
+    const int32_t x = (int32_t)(px % W), y = (int32_t)(px / W);
+    const PairDesc pd = pairs[p];
+    const FrameDesc f1 = frames[pd.f1], f2 = frames[pd.f2];
+    const float u = pd.out[px], v = pd.out[(int64_t)W * H + px];
+    const float fu = floorf(u), fv = floorf(v);
+    int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
+    float fx = u - fu, fy = v - fv;
+    if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
+    if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
+    const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
+    const uint8_t* a = f2.y;
+    const float top = (1.f - fx) * a[(int64_t)yi * f2.pitch + xi] + fx * a[(int64_t)yi * f2.pitch + x1];
+    const float bot = (1.f - fx) * a[(int64_t)y1 * f2.pitch + xi] + fx * a[(int64_t)y1 * f2.pitch + x1];
+    r = fabsf((1.f - fy) * top + fy * bot - (float)f1.y[(int64_t)y * f1.pitch + x]);
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_gate_final(const float* __restrict__ part, int32_t blocks_per_pair, int64_t n_pairs, float inv_px,
+                             float tau, const PairDesc* __restrict__ pairs, uint8_t* __restrict__ active) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  float s = 0.f;
+  for (int b = 0; b < blocks_per_pair; ++b) s += part[p * blocks_per_pair + b];
+  const float r = s * inv_px;
+  const uint8_t a = r > tau ? 1 : 0;
+  active[p] = a;
+  const PairDesc pd = pairs[p];
+  if (pd.resid) *pd.resid = r;
+  if (pd.fb) *pd.fb = a;
+}
+
+// frame slots used by at least one active pair (factive zeroed beforehand)
+__global__ void k_mark_frames(const PairDesc* __restrict__ pairs, const uint8_t* __restrict__ active,
+                              uint8_t* __restrict__ factive, int64_t n_pairs) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n_pairs || !active[p]) return;
+  factive[pairs[p].f1] = 1;
+  factive[pairs[p].f2] = 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host orchestration
+
+struct NetBuffers {
+  bf16_t* x;
+  bf16_t* act[kLayers - 1];
+  float* half;
+  // training only
+  float* ghalf;
+  float* dxe;
+  bf16_t* g[2];
+  float* part;
+  float* partb;
+  float* loss_part;
+};
+
+struct NetDims {
+  int32_t h, w;  // half resolution
+  int32_t hl[kLayers + 1], wl[kLayers + 1];  // stored size of each layer's output (index l+1), input at 0
+};
+
+NetDims net_dims(int32_t W, int32_t H) {
+  NetDims d;
+  d.h = H / 2;
+  d.w = W / 2;
+  d.hl[0] = d.h;
+  d.wl[0] = d.w;
+  for (int l = 0; l < kLayers; ++l) {
+    const int he = kNet[l].up ? 2 * d.hl[l] : d.hl[l], we = kNet[l].up ? 2 * d.wl[l] : d.wl[l];
+    d.hl[l + 1] = (he - 1) / kNet[l].stride + 1;
+    d.wl[l + 1] = (we - 1) / kNet[l].stride + 1;
+  }
+  return d;
+}
+
+constexpr int64_t kDwChunk = 2048;  // pixels per weight-gradient workgroup
+
+struct NetLayout {
+  size_t bytes = 0;
+  size_t off_x = 0, off_act[kLayers - 1] = {}, off_half = 0, off_ghalf = 0, off_dxe = 0, off_g[2] = {}, off_part = 0,
+         off_partb = 0, off_loss = 0;
+};
+
+NetLayout net_layout(int32_t W, int32_t H, int64_t n, bool training) {
+  const NetDims d = net_dims(W, H);
+  NetLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t r = o;
+    o += align_up(b);
+    return r;
+  };
+  L.off_x = take((size_t)n * d.h * d.w * 2 * 2);
+  for (int l = 0; l < kLayers - 1; ++l) L.off_act[l] = take((size_t)n * d.hl[l + 1] * d.wl[l + 1] * kNet[l].co * 2);
+  L.off_half = take((size_t)n * d.h * d.w * 2 * 4);
+  if (training) {
+    L.off_ghalf = take((size_t)n * d.h * d.w * 2 * 4);
+    size_t dxe = 0, gmax = 0, part = 0, partb = 0;
+    for (int l = 1; l < kLayers; ++l) {
+      const int he = kNet[l].up ? 2 * d.hl[l] : d.hl[l], we = kNet[l].up ? 2 * d.wl[l] : d.wl[l];
+      dxe = std::max(dxe, (size_t)n * he * we * kNet[l].ci * 4);
+      gmax = std::max(gmax, (size_t)n * d.hl[l] * d.wl[l] * kNet[l].ci * 2);
+    }
+    for (int l = 0; l < kLayers; ++l) {
+      const int64_t M = n * (int64_t)d.hl[l + 1] * d.wl[l + 1];
+      const int64_t chunks = (M + kDwChunk - 1) / kDwChunk;
+      part = std::max(part, (size_t)chunks * 9 * kNet[l].co * kNet[l].ci * 4);
+      partb = std::max(partb, (size_t)chunks * kNet[l].co * 4);
+    }
+    L.off_dxe = take(dxe);
+    L.off_g[0] = take(gmax);
+    L.off_g[1] = take(gmax);
+    L.off_part = take(part);
+    L.off_partb = take(partb);
+    L.off_loss = take((size_t)((n * d.h * d.w + 255) / 256 + 1) * 4);
+  }
+  L.bytes = o;
+  return L;
+}
+
+NetBuffers net_buffers(uint8_t* base, const NetLayout& L, bool training) {
+  NetBuffers b{};
+  b.x = reinterpret_cast<bf16_t*>(base + L.off_x);
+  for (int l = 0; l < kLayers - 1; ++l) b.act[l] = reinterpret_cast<bf16_t*>(base + L.off_act[l]);
+  b.half = reinterpret_cast<float*>(base + L.off_half);
+  if (training) {
+    b.ghalf = reinterpret_cast<float*>(base + L.off_ghalf);
+    b.dxe = reinterpret_cast<float*>(base + L.off_dxe);
+    b.g[0] = reinterpret_cast<bf16_t*>(base + L.off_g[0]);
+    b.g[1] = reinterpret_cast<bf16_t*>(base + L.off_g[1]);
+    b.part = reinterpret_cast<float*>(base + L.off_part);
+    b.partb = reinterpret_cast<float*>(base + L.off_partb);
+    b.loss_part = reinterpret_cast<float*>(base + L.off_loss);
+  }
+  return b;
+}
+
+CGeom layer_geom(const NetDims& d, int l, int64_t n) {
+  CGeom g;
+  g.n = (int32_t)n;
+  g.hi = d.hl[l];
+  g.wi = d.wl[l];
+  g.he = kNet[l].up ? 2 * g.hi : g.hi;
+  g.we = kNet[l].up ? 2 * g.wi : g.wi;
+  g.ho = d.hl[l + 1];
+  g.wo = d.wl[l + 1];
+  return g;
+}
+
+constexpr int kMR = 2;  // 16-pixel row blocks per wave
+
+template <int L>
+scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom& g, hipStream_t s) {
+  const int64_t M = (int64_t)g.n * g.ho * g.wo;
+  const int64_t per_wg = 4 * 16 * kMR;
+  const int64_t grid = (M + per_wg - 1) / per_wg;
+  KernelTimer timer("conv_fwd", s);
+  hipLaunchKernelGGL((k_conv_fwd<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g);
+  SCN_LAUNCHED("conv forward launch");
+  return SCN_OK;
+}
+
+template <int L>
+scn_status launch_dx(const void* dy, const uint8_t* blob, float* dxe, const CGeom& g, hipStream_t s) {
+  const int64_t M = (int64_t)g.n * g.he * g.we;
+  const int64_t per_wg = 4 * 16 * kMR;
+  const int64_t grid = (M + per_wg - 1) / per_wg;
+  KernelTimer timer("conv_dx", s);
+  hipLaunchKernelGGL((k_conv_dx<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, dy, blob, dxe, g);
+  SCN_LAUNCHED("conv input-gradient launch");
+  return SCN_OK;
+}
+
+template <int L>
+scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float* grads, const CGeom& g,
+                     hipStream_t s) {
+  const int64_t M = (int64_t)g.n * g.ho * g.wo;
+  const int64_t chunks = (M + kDwChunk - 1) / kDwChunk;
+  {
+    KernelTimer timer("conv_dw", s);
+    hipLaunchKernelGGL((k_conv_dw<L>), dim3((unsigned)(chunks * 9)), dim3(256), 0, s, dy, x, b.part, b.partb, g,
+                       (int32_t)kDwChunk);
+  }
+  SCN_LAUNCHED("conv weight-gradient launch");
+  const int64_t n = (int64_t)kNet[L].co * kNet[L].ci * 9 + kNet[L].co;
+  hipLaunchKernelGGL(k_dw_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.part, b.partb, grads, chunks,
+                     kNet[L].ci, kNet[L].co, param_w_off(L), param_b_off(L));
+  SCN_LAUNCHED("weight-gradient reduce launch");
+  return SCN_OK;
+}
+
+scn_status net_forward(const NetDims& d, int64_t n, const uint8_t* blob, const NetBuffers& b, hipStream_t s) {
+  scn_status st;
+  if ((st = launch_fwd<0>(b.x, blob, b.act[0], layer_geom(d, 0, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<1>(b.act[0], blob, b.act[1], layer_geom(d, 1, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<2>(b.act[1], blob, b.act[2], layer_geom(d, 2, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<3>(b.act[2], blob, b.act[3], layer_geom(d, 3, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<4>(b.act[3], blob, b.act[4], layer_geom(d, 4, n), s)) != SCN_OK) return st;
+  return launch_fwd<5>(b.act[4], blob, b.half, layer_geom(d, 5, n), s);
+}
+
+scn_status dx_post(const float* dxe, const bf16_t* act, bf16_t* gout, const NetDims& d, int l_prev_out, int64_t n,
+                   int up, hipStream_t s) {
+  // l_prev_out: index of the stored activation (layer output l_prev_out) the gradient belongs to
+  const int32_t h = d.hl[l_prev_out + 1], w = d.wl[l_prev_out + 1], c = kNet[l_prev_out].co;
+  const int64_t ne = n * h * w * c;
+  hipLaunchKernelGGL(k_dx_post, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, dxe, act, gout, ne, h, w, c, up);
+  SCN_LAUNCHED("input-gradient post launch");
+  return SCN_OK;
+}
+
+scn_status net_backward(const NetDims& d, int64_t n, const uint8_t* blob, const NetBuffers& b, float* grads,
+                        hipStream_t s) {
+  scn_status st;
+  // conv6: dy = ghalf (FP32), input act5
+  if ((st = launch_dw<5>(b.ghalf, b.act[4], b, grads, layer_geom(d, 5, n), s)) != SCN_OK) return st;
+  if ((st = launch_dx<5>(b.ghalf, blob, b.dxe, layer_geom(d, 5, n), s)) != SCN_OK) return st;
+  if ((st = dx_post(b.dxe, b.act[4], b.g[0], d, 4, n, 0, s)) != SCN_OK) return st;
+  // conv5: dy = g[0], input up(act4)
+  if ((st = launch_dw<4>(b.g[0], b.act[3], b, grads, layer_geom(d, 4, n), s)) != SCN_OK) return st;
+  if ((st = launch_dx<4>(b.g[0], blob, b.dxe, layer_geom(d, 4, n), s)) != SCN_OK) return st;
+  if ((st = dx_post(b.dxe, b.act[3], b.g[1], d, 3, n, 1, s)) != SCN_OK) return st;
+  // conv4: dy = g[1], input up(act3)
+  if ((st = launch_dw<3>(b.g[1], b.act[2], b, grads, layer_geom(d, 3, n), s)) != SCN_OK) return st;
+  if ((st = launch_dx<3>(b.g[1], blob, b.dxe, layer_geom(d, 3, n), s)) != SCN_OK) return st;
+  if ((st = dx_post(b.dxe, b.act[2], b.g[0], d, 2, n, 1, s)) != SCN_OK) return st;
+  // conv3: dy = g[0], input act2 (stride 2)
+  if ((st = launch_dw<2>(b.g[0], b.act[1], b, grads, layer_geom(d, 2, n), s)) != SCN_OK) return st;
+  if ((st = launch_dx<2>(b.g[0], blob, b.dxe, layer_geom(d, 2, n), s)) != SCN_OK) return st;
+  if ((st = dx_post(b.dxe, b.act[1], b.g[1], d, 1, n, 0, s)) != SCN_OK) return st;
+  // conv2: dy = g[1], input act1 (stride 2)
+  if ((st = launch_dw<1>(b.g[1], b.act[0], b, grads, layer_geom(d, 1, n), s)) != SCN_OK) return st;
+  if ((st = launch_dx<1>(b.g[1], blob, b.dxe, layer_geom(d, 1, n), s)) != SCN_OK) return st;
+  if ((st = dx_post(b.dxe, b.act[0], b.g[0], d, 0, n, 0, s)) != SCN_OK) return st;
+  // conv1: dy = g[0], input x
+  return launch_dw<0>(b.g[0], b.x, b, grads, layer_geom(d, 0, n), s);
+}
+
+scn_status launch_net_input(const FrameDesc* frames, const PairDesc* pairs, bf16_t* x, const NetDims& d, int64_t n,
+                            hipStream_t s) {
+  const int64_t ne = n * d.h * d.w;
+  hipLaunchKernelGGL(k_net_input, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, frames, pairs, x, d.h, d.w, n);
+  SCN_LAUNCHED("network input launch");
+  return SCN_OK;
+}
+
+scn_status launch_flow_up(const float* half, const PairDesc* pairs, const NetDims& d, int64_t n, hipStream_t s) {
+  const int64_t ne = n * 4 * (int64_t)d.h * d.w;
+  KernelTimer timer("flow_up", s);
+  hipLaunchKernelGGL(k_flow_up, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, half, pairs, d.h, d.w, n);
+  SCN_LAUNCHED("flow upsample launch");
+  return SCN_OK;
+}
+
+scn_status launch_gate(const FrameDesc* frames, const PairDesc* pairs, float* part, int32_t W, int32_t H, int64_t n,
+                       float tau, uint8_t* active, hipStream_t s) {
+  const int32_t bpp = (int32_t)(((int64_t)W * H + 255) / 256);
+  KernelTimer timer("gate", s);
+  hipLaunchKernelGGL(k_gate_partial, dim3((unsigned)(bpp * n)), dim3(256), 0, s, frames, pairs, part, W, H, bpp);
+  SCN_LAUNCHED("gate launch");
+  hipLaunchKernelGGL(k_gate_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, bpp, n,
+                     1.f / ((float)W * H), tau, pairs, active);
+  SCN_LAUNCHED("gate reduce launch");
+  return SCN_OK;
+}
+
+size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) { return align_up((size_t)n * (((size_t)W * H + 255) / 256) * 4); }
+
+}  // namespace sg
+
+scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
+                          const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
+                          hipStream_t s);
+
+namespace {
+
+const scn_flow_params kNoFlowParams = {1, 1.f, 0, 0, 0, 0};
+
+size_t surrogate_extra(int32_t w, int32_t h) {
+  const sg::NetLayout L = sg::net_layout(w, h, 1, false);
+  return L.bytes + sg::gate_part_bytes(w, h, 1) + 2 * 256 + 32 * 256;
+}
+
+scn_status check_net_shape(const FlowPlan& plan) {
+  for (const FlowGroup& g : plan.groups)
+    if (g.w % 8 || g.h % 8) {
+      set_error("the surrogate needs width and height that are multiples of 8");
+      return SCN_EUNSUPPORTED;
+    }
+  return SCN_OK;
+}
+
+// grads / infer: every pair of the call in one batch of one resolution
+scn_status batch_plan(const scn_job* jobs, int32_t n_jobs, float* const* outs, FlowPlan* plan, bool training,
+                      size_t* need) {
+  scn_status st = build_flow_plan(jobs, n_jobs, &kNoFlowParams, outs, 0, plan);
+  if (st != SCN_OK) return st;
+  if (plan->groups.size() > 1) {
+    set_error("surrogate training and inference batches need one resolution");
+    return SCN_EUNSUPPORTED;
+  }
+  if ((st = check_net_shape(*plan)) != SCN_OK) return st;
+  *need = plan->scratch_off;
+  if (!plan->groups.empty())
+    *need += sg::net_layout(plan->groups[0].w, plan->groups[0].h, plan->groups[0].total_pairs, training).bytes;
+  return SCN_OK;
+}
+
+}  // namespace
+
+size_t surrogate_ws_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p) {
+  FlowPlan plan;
+  size_t need = 0;
+  if (op == SCN_OP_SURROGATE) {
+    if (build_flow_plan(jobs, n_jobs, p, nullptr, 0, &plan, surrogate_extra) != SCN_OK) return 0;
+    if (check_net_shape(plan) != SCN_OK) return 0;
+    return plan.ws_needed;
+  }
+  if (batch_plan(jobs, n_jobs, nullptr, &plan, op == SCN_OP_SURROGATE_GRADS, &need) != SCN_OK) return 0;
+  return need;
+}
+
+}  // namespace scn
+
+using namespace scn;
+
+extern "C" {
+
+size_t scn_net_bytes(void) { return (size_t)sg::kBlobBytes; }
+
+int32_t scn_net_params(void) { return sg::kParams; }
+
+scn_status scn_net_pack(const float* master, void* net, scn_stream_t stream) {
+  clear_error();
+  if (!master || !net) { set_error("NULL argument"); return SCN_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t words = sg::kBlobBytes / 4;
+  hipLaunchKernelGGL(sg::k_zero_bytes, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)net, words);
+  SCN_LAUNCHED("net zero launch");
+  hipLaunchKernelGGL(sg::k_pack, dim3((sg::kParams + 255) / 256), dim3(256), 0, s, master, (uint8_t*)net);
+  SCN_LAUNCHED("net pack launch");
+  return SCN_OK;
+}
+
+scn_status scn_adam_step(float* master, float* m, float* v, const float* grads, int32_t step, float lr, float beta1,
+                         float beta2, float eps, void* net, scn_stream_t stream) {
+  clear_error();
+  if (!master || !m || !v || !grads || !net) { set_error("NULL argument"); return SCN_EINVAL; }
+  if (step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
+    set_error("bad Adam hyper-parameters");
+    return SCN_EINVAL;
+  }
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  hipLaunchKernelGGL(sg::k_adam, dim3((sg::kParams + 255) / 256), dim3(256), 0, (hipStream_t)stream, master, m, v,
+                     grads, lr, beta1, beta2, eps, bc1, bc2, (uint8_t*)net);
+  SCN_LAUNCHED("adam launch");
+  return SCN_OK;
+}
+
+scn_status scn_surrogate_grads(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* targets,
+                               float* grads, float* loss, void* ws, size_t ws_bytes, scn_stream_t stream) {
+  clear_error();
+  FlowPlan plan;
+  size_t need = 0;
+  scn_status st = batch_plan(jobs, n_jobs, targets, &plan, true, &need);
+  if (st != SCN_OK) return st;
+  if (plan.total_pairs == 0) { set_error("no pairs"); return SCN_EINVAL; }
+  if (!net || !grads || !loss || !ws) { set_error("NULL argument"); return SCN_EINVAL; }
+  if (ws_bytes < need) { set_error("workspace too small for surrogate gradients"); return SCN_ENOSPACE; }
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s)) != SCN_OK) return st;
+  const FlowGroup& grp = plan.groups[0];
+  const FlowChunk& ch = grp.chunks[0];
+  uint8_t* base = (uint8_t*)ws;
+  const sg::NetLayout L = sg::net_layout(grp.w, grp.h, ch.n_pairs, true);
+  const sg::NetBuffers b = sg::net_buffers(base + plan.scratch_off, L, true);
+  const sg::NetDims d = sg::net_dims(grp.w, grp.h);
+  const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
+  const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
+  const uint8_t* blob = (const uint8_t*)net;
+  const int64_t n = ch.n_pairs;
+  if ((st = sg::launch_net_input(frames, pairs, b.x, d, n, s)) != SCN_OK) return st;
+  if ((st = sg::net_forward(d, n, blob, b, s)) != SCN_OK) return st;
+  const int64_t nh = n * d.h * d.w;
+  const int64_t blocks = (nh + 255) / 256;
+  const float scale = 1.f / ((float)grp.w * grp.h * (float)n);
+  hipLaunchKernelGGL(sg::k_loss_grad, dim3((unsigned)blocks), dim3(256), 0, s, b.half, pairs, b.ghalf, b.loss_part,
+                     d.h, d.w, n, scale);
+  SCN_LAUNCHED("loss launch");
+  hipLaunchKernelGGL(sg::k_sum_loss, dim3(1), dim3(256), 0, s, b.loss_part, blocks, scale, loss);
+  SCN_LAUNCHED("loss reduce launch");
+  return sg::net_backward(d, n, blob, b, grads, s);
+}
+
+scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* flow, void* ws,
+                               size_t ws_bytes, scn_stream_t stream) {
+  clear_error();
+  FlowPlan plan;
+  size_t need = 0;
+  scn_status st = batch_plan(jobs, n_jobs, flow, &plan, false, &need);
+  if (st != SCN_OK) return st;
+  if (plan.total_pairs == 0) return SCN_OK;
+  if (!net || !ws) { set_error("NULL argument"); return SCN_EINVAL; }
+  if (ws_bytes < need) { set_error("workspace too small for surrogate inference"); return SCN_ENOSPACE; }
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s)) != SCN_OK) return st;
+  const FlowGroup& grp = plan.groups[0];
+  const FlowChunk& ch = grp.chunks[0];
+  uint8_t* base = (uint8_t*)ws;
+  const sg::NetLayout L = sg::net_layout(grp.w, grp.h, ch.n_pairs, false);
+  const sg::NetBuffers b = sg::net_buffers(base + plan.scratch_off, L, false);
+  const sg::NetDims d = sg::net_dims(grp.w, grp.h);
+  const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
+  const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
+  if ((st = sg::launch_net_input(frames, pairs, b.x, d, ch.n_pairs, s)) != SCN_OK) return st;
+  if ((st = sg::net_forward(d, ch.n_pairs, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+  return sg::launch_flow_up(b.half, pairs, d, ch.n_pairs, s);
+}
+
+scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* fallback_p, const void* net,
+                              float gate_tau, float* const* flow, uint8_t* const* fell_back, float* const* residual,
+                              void* ws, size_t ws_bytes, scn_stream_t stream) {
+  clear_error();
+  FlowPlan plan;
+  scn_status st = build_flow_plan(jobs, n_jobs, fallback_p, flow, ws_bytes, &plan, surrogate_extra, fell_back,
+                                  residual);
+  if (st != SCN_OK) return st;
+  if ((st = check_net_shape(plan)) != SCN_OK) return st;
+  if (plan.total_pairs == 0) return SCN_OK;
+  if (!net || !ws) { set_error("NULL argument"); return SCN_EINVAL; }
+  if (!(gate_tau >= 0.f)) { set_error("gate_tau must be >= 0"); return SCN_EINVAL; }
+  if (ws_bytes < plan.ws_min) { set_error("workspace too small for the surrogate path"); return SCN_ENOSPACE; }
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s)) != SCN_OK) return st;
+  uint8_t* base = (uint8_t*)ws;
+  for (const FlowGroup& grp : plan.groups) {
+    const sg::NetDims d = sg::net_dims(grp.w, grp.h);
+    for (const FlowChunk& ch : grp.chunks) {
+      const int64_t n = ch.n_pairs;
+      uint8_t* extra = base + plan.scratch_off + chunk_pyr_bytes(grp, ch) + chunk_pairs_bytes(grp, ch);
+      const sg::NetLayout L = sg::net_layout(grp.w, grp.h, n, false);
+      const sg::NetBuffers b = sg::net_buffers(extra, L, false);
+      float* gpart = (float*)(extra + L.bytes);
+      uint8_t* active = extra + L.bytes + sg::gate_part_bytes(grp.w, grp.h, n);
+      uint8_t* factive = active + align_up((size_t)n);
+      const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
+      const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
+      if ((st = sg::launch_net_input(frames, pairs, b.x, d, n, s)) != SCN_OK) return st;
+      if ((st = sg::net_forward(d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+      if ((st = sg::launch_flow_up(b.half, pairs, d, n, s)) != SCN_OK) return st;
+      if ((st = sg::launch_gate(frames, pairs, gpart, grp.w, grp.h, n, gate_tau, active, s)) != SCN_OK) return st;
+      const int64_t fw = (ch.n_frames + 3) / 4;
+      hipLaunchKernelGGL(sg::k_zero_bytes, dim3((unsigned)((fw + 255) / 256)), dim3(256), 0, s, (uint32_t*)factive,
+                         fw);
+      hipLaunchKernelGGL(sg::k_mark_frames, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pairs, active,
+                         factive, n);
+      SCN_LAUNCHED("fallback frame marking launch");
+      if ((st = run_flow_chunk(plan, grp, ch, *fallback_p, ws, active, factive, s)) != SCN_OK) return st;
+    }
+  }
+  return SCN_OK;
+}
+
+}  // extern "C"

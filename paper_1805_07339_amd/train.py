@@ -1,0 +1,206 @@
+"""Training loop, gate calibration and checkpoints of the learned flow surrogate.
+
+Every step runs in libscn's kernels: labels come from the plain Horn-Schunck
+solver (scn_flow), gradients from scn_surrogate_grads (BF16 MFMA forward and
+backward), updates from scn_adam_step.  This module only schedules batches,
+holds the buffers and writes checkpoints.
+
+    python -m paper_1805_07339_amd.train --pairs 20000 --epochs 15 --out weights/surrogate.safetensors
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+import torch
+
+import paper_1805_07339_amd as scn
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(PKG, "weights", "surrogate.safetensors")
+
+
+def he_init(seed: int) -> torch.Tensor:
+    """He-normal weights (std sqrt(2 / fan_in); conv6 scaled by 0.1), zero biases, as
+    the FP32 master vector.  Normals come from SplitMix64 + Box-Muller."""
+    from synth import SplitMix64
+    layers = [(2, 32), (32, 64), (64, 96), (96, 64), (64, 32), (32, 2)]
+    rng = SplitMix64(seed)
+    out = []
+    for i, (ci, co) in enumerate(layers):
+        std = math.sqrt(2.0 / (ci * 9)) * (0.1 if i == len(layers) - 1 else 1.0)
+        out.append(np.array([rng.normal() * std for _ in range(co * ci * 9)], dtype=np.float32))
+        out.append(np.zeros(co, dtype=np.float32))
+    v = np.concatenate(out)
+    assert v.size == scn.net_params()
+    return torch.from_numpy(v)
+
+
+class PairSet:
+    """Synthetic training pairs resident in HBM: rows 2i and 2i+1 of one table
+    hold pair i, so a batch is a RANGE job of disjoint 2-row windows."""
+
+    def __init__(self, n_pairs: int, width: int = 512, height: int = 384, seed: int = 4_000_000,
+                 frames_per_scene: int = 40, device="cuda", max_step: int = 3):
+        import synth
+        self.n, self.W, self.H = n_pairs, width, height
+        fb = width * height * 3 // 2
+        self.table = torch.empty((2 * n_pairs, fb), dtype=torch.uint8, device=device)
+        rng = synth.SplitMix64(seed)
+        i = 0
+        scene_id = 0
+        while i < n_pairs:
+            scene = synth.layered_scene(seed + scene_id, width, height)
+            scene_id += 1
+            k = min(frames_per_scene, n_pairs - i)
+            t0 = [rng.randint(1000) for _ in range(k)]
+            dt = [1 + rng.randint(max_step) for _ in range(k)]
+            a = synth.scene_batch_nv12(scene, t0, device, 0)
+            b = synth.scene_batch_nv12(scene, [x + d for x, d in zip(t0, dt)], device, 1)
+            self.table[2 * i:2 * (i + k):2] = a.reshape(k, -1)
+            self.table[2 * i + 1:2 * (i + k):2] = b.reshape(k, -1)
+            i += k
+        self.tab = scn.Table.from_tensor(self.table, width, height)
+        self.labels: Optional[torch.Tensor] = None
+
+    def job(self, idx) -> scn.Job:
+        idx = sorted(int(k) for k in idx)
+        return scn.Job(self.tab, scn.Sampling.range([(2 * k, 2 * k + 2) for k in idx]))
+
+    def label_all(self, params=None, chunk: int = 1024):
+        """Plain Horn-Schunck flow of every pair (the training targets)."""
+        params = scn.flow_params(4, 10.0, 50) if params is None else params
+        self.labels = torch.empty((self.n, 2, self.H, self.W), dtype=torch.float32, device=self.table.device)
+        for s in range(0, self.n, chunk):
+            idx = list(range(s, min(self.n, s + chunk)))
+            scn.flow([self.job(idx)], params, outs=[self.labels[s:s + len(idx)]])
+        torch.cuda.synchronize()
+
+
+def cosine_lr(step: int, total: int, lr0: float = 1e-3, lr1: float = 1e-5) -> float:
+    return lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * min(step, total) / max(total, 1)))
+
+
+def train(data: PairSet, epochs: int = 15, batch: int = 32, seed: int = 1, lr0: float = 1e-3, lr1: float = 1e-5,
+          log_every: int = 200, master: Optional[torch.Tensor] = None, log=print):
+    dev = data.table.device
+    master = (he_init(seed) if master is None else master).to(dev)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    net = scn.net_pack(master)
+    g = torch.Generator().manual_seed(seed)
+    steps_per_epoch = data.n // batch
+    total = epochs * steps_per_epoch
+    tgt = torch.empty((batch, 2, data.H, data.W), dtype=torch.float32, device=dev)
+    step = 0
+    hist = []
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.randperm(data.n, generator=g)
+        for b in range(steps_per_epoch):
+            idx = sorted(perm[b * batch:(b + 1) * batch].tolist())
+            torch.index_select(data.labels, 0, torch.tensor(idx, device=dev), out=tgt)
+            grads, loss = scn.surrogate_grads([data.job(idx)], net, [tgt])
+            step += 1
+            scn.adam_step(master, m, v, grads, step, cosine_lr(step, total, lr0, lr1), net)
+            if step % log_every == 0 or step == total:
+                lv = float(loss.item())
+                hist.append((step, lv))
+                log("epoch %d step %d/%d loss %.4f lr %.2e %.1fs" % (ep, step, total, lv,
+                                                                      cosine_lr(step, total, lr0, lr1),
+                                                                      time.time() - t0))
+    return master, m, v, net, step, hist
+
+
+def calibrate_tau(net: torch.Tensor, jobs: List[scn.Job], plain: List[torch.Tensor], target_epe: float = 0.4,
+                  ) -> Tuple[float, Dict]:
+    """Largest tau whose mean EPE against plain flow (fallback pairs count as 0) is <= target_epe."""
+    flows = scn.surrogate_infer(jobs, net)
+    res, epes = [], []
+    for j, f, p in zip(jobs, flows, plain):
+        _, (_,), (r,) = scn.flow_surrogate([j], net, 1e30)
+        res.append(r.cpu().numpy())
+        epes.append(torch.sqrt(((f - p) ** 2).sum(dim=1)).mean(dim=(1, 2)).cpu().numpy())
+    r = np.concatenate(res).astype(np.float64)
+    e = np.concatenate(epes).astype(np.float64)
+    order = np.argsort(r)
+    r, e = r[order], e[order]
+    n = len(r)
+    best = -1.0
+    kept = 0
+    for k in range(n + 1):  # keep the k lowest-residual pairs
+        mean_epe = e[:k].sum() / n
+        if mean_epe <= target_epe:
+            tau = r[k - 1] if k > 0 else -1.0
+            if k == n or r[k] > tau:
+                best, kept = tau, k
+    info = {"pairs": n, "kept": kept, "mean_epe_all_surrogate": float(e.mean()),
+            "median_residual": float(np.median(r))}
+    return float(max(best, 0.0)) if kept > 0 else 0.0, info
+
+
+def save(path: str, master: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, meta: Dict):
+    from safetensors.torch import save_file
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    save_file({"master": master.detach().cpu().contiguous(), "adam_m": m.detach().cpu().contiguous(),
+               "adam_v": v.detach().cpu().contiguous()},
+              path, metadata={"step": str(step), "meta": json.dumps(meta)})
+
+
+def load(path: str = DEFAULT_WEIGHTS, device="cuda"):
+    """(master FP32 vector on device, metadata dict)."""
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        master = f.get_tensor("master").to(device)
+        meta = json.loads(f.metadata().get("meta", "{}"))
+        meta["step"] = int(f.metadata().get("step", "0"))
+    return master, meta
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=15)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--calib-pairs", type=int, default=64)
+    args = ap.parse_args()
+    t0 = time.time()
+    data = PairSet(args.pairs)
+    print("data %.1fs" % (time.time() - t0), flush=True)
+    data.label_all()
+    print("labels %.1fs" % (time.time() - t0), flush=True)
+    master, m, v, net, step, hist = train(data, args.epochs, args.batch, args.seed,
+                                          log=lambda s: print(s, flush=True))
+    train_s = time.time() - t0
+    del data
+    torch.cuda.empty_cache()
+    # calibrate the gate on held-out 1080p pairs of the layered-scene family
+    import synth
+    W, H = 1920, 1080
+    jobs, plain = [], []
+    for sd in (21, 22):
+        sc = synth.layered_scene(sd, W, H)
+        rows = list(range(0, 24 * (args.calib_pairs // 2 + 1), 24))
+        frames = torch.stack([sc.nv12(r, device="cuda").reshape(-1) for r in rows])
+        tab = scn.Table.from_tensor(frames, W, H)
+        j = scn.Job(tab, scn.Sampling.stride(1, 0, len(rows)))
+        jobs.append(j)
+        (p,) = scn.flow([j], scn.flow_params(4, 10.0, 50))
+        plain.append(p)
+    tau, info = calibrate_tau(net, jobs, plain)
+    meta = {"tau": tau, "calibration": info, "train_pairs": args.pairs, "epochs": args.epochs,
+            "batch": args.batch, "seed": args.seed, "train_seconds": train_s, "loss_history": hist[-20:]}
+    save(args.out, master, m, v, step, meta)
+    print(json.dumps({"tau": tau, **info, "train_seconds": train_s}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -220,6 +220,73 @@ class Scene:
         return out
 
 
+def eval_grid_batch(tex: Texture, xs: torch.Tensor, ys: torch.Tensor, Ms, cs) -> torch.Tensor:
+    """tex(M_b @ (x, y) + c_b) for a batch of maps (float64 [B, len(ys), len(xs)])."""
+    dev = xs.device
+    fx = torch.tensor(tex.fx, dtype=torch.float64, device=dev)
+    fy = torch.tensor(tex.fy, dtype=torch.float64, device=dev)
+    ph = torch.tensor(tex.phase, dtype=torch.float64, device=dev)
+    M = torch.tensor(Ms, dtype=torch.float64, device=dev)          # [B, 2, 2]
+    c = torch.tensor(cs, dtype=torch.float64, device=dev)          # [B, 2]
+    two_pi = 2.0 * math.pi
+    gx = two_pi * (M[:, 0, 0, None] * fx + M[:, 1, 0, None] * fy)  # [B, K]
+    gy = two_pi * (M[:, 0, 1, None] * fx + M[:, 1, 1, None] * fy)
+    gam = two_pi * (c[:, 0, None] * fx + c[:, 1, None] * fy) + ph
+    ax = gx[:, :, None] * xs[None, None, :] + gam[:, :, None]      # [B, K, W]
+    ay = gy[:, :, None] * ys[None, None, :]                        # [B, K, H]
+    left = torch.cat([torch.cos(ay), -torch.sin(ay)], 1).transpose(1, 2)  # [B, H, 2K]
+    right = torch.cat([torch.cos(ax), torch.sin(ax)], 1)                   # [B, 2K, W]
+    return tex.mean + tex.amp * torch.bmm(left, right)
+
+
+def scene_batch_nv12(scene: "Scene", ts: Sequence[int], device="cpu", seed_salt: int = 0) -> torch.Tensor:
+    """uint8 NV12 frames [B, H*3/2, W] of one layered scene at time steps ts,
+    evaluated for all time steps at once (same model as Scene.nv12; the noise
+    stream differs)."""
+    W, H = scene.width, scene.height
+    dev = torch.device(device)
+    B = len(ts)
+    xs = torch.arange(W, dtype=torch.float64, device=dev)
+    ys = torch.arange(H, dtype=torch.float64, device=dev)
+    cxs = 2.0 * torch.arange(W // 2, dtype=torch.float64, device=dev) + 0.5
+    cys = 2.0 * torch.arange(H // 2, dtype=torch.float64, device=dev) + 0.5
+    Y = U = V = None
+    for lay in scene.layers:
+        maps = [lay.inverse_map(t) for t in ts]
+        Ms = [m for m, _ in maps]
+        cs = [c for _, c in maps]
+        ty = eval_grid_batch(lay.tex_y, xs, ys, Ms, cs)
+        tu = eval_grid_batch(lay.tex_u, cxs, cys, Ms, cs)
+        tv = eval_grid_batch(lay.tex_v, cxs, cys, Ms, cs)
+        if lay.shape == "full":
+            Y, U, V = ty, tu, tv
+            continue
+        M = torch.tensor(Ms, dtype=torch.float64, device=dev)
+        c = torch.tensor(cs, dtype=torch.float64, device=dev)
+
+        def qmap(px, py):
+            qx = M[:, 0, 0, None, None] * px[None, None, :] + M[:, 0, 1, None, None] * py[None, :, None] + c[:, 0, None, None]
+            qy = M[:, 1, 0, None, None] * px[None, None, :] + M[:, 1, 1, None, None] * py[None, :, None] + c[:, 1, None, None]
+            return qx, qy
+        m = lay.mask(*qmap(xs, ys))
+        Y = torch.where(m, ty, Y)
+        mc = lay.mask(*qmap(cxs, cys))
+        U = torch.where(mc, tu, U)
+        V = torch.where(mc, tv, V)
+    g = torch.Generator(device=dev)
+    g.manual_seed((scene.seed * 1_000_003 + 104729 * (seed_salt + 1) + int(ts[0])) & 0x7FFFFFFFFFFFFFFF)
+    s = scene.noise_sigma
+    if s > 0:
+        Y = Y + s * torch.randn(Y.shape, generator=g, dtype=torch.float64, device=dev)
+        U = U + s * torch.randn(U.shape, generator=g, dtype=torch.float64, device=dev)
+        V = V + s * torch.randn(V.shape, generator=g, dtype=torch.float64, device=dev)
+    q = lambda a: torch.clamp(torch.round(a), 0, 255).to(torch.uint8)
+    out = torch.empty(B, H * 3 // 2, W, dtype=torch.uint8, device=dev)
+    out[:, :H] = q(Y)
+    out[:, H:] = torch.stack([q(U), q(V)], dim=-1).reshape(B, H // 2, W)
+    return out
+
+
 def translation_scene(seed: int, width: int, height: int, n_frames: int, max_shift: float = 2.0,
                       noise_sigma: float = 2.0) -> Tuple[Scene, List[Tuple[float, float]]]:
     """One texture translated per frame: frame t = T(x - sum_{k<t} d_k), |d_k| <= max_shift.
