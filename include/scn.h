@@ -102,8 +102,9 @@ typedef struct {
  * SCN_TUNE_CACHE / SCN_TUNE in the implementation notes); sweeps_per_pass = 1
  * with tile_variant = 0 runs one sweep per launch; otherwise sweeps_per_pass
  * sweeps (1..63) run per launch on register tiles of variant 1..4 (128 x 128,
- * 128 x 128, 128 x 64, 128 x 64 pixels).  Every schedule gives bitwise
- * identical results. */
+ * 128 x 128, 128 x 64, 128 x 64 pixels), or on 128-column strips streamed
+ * row by row with variants 5..7 (at most 6, 8, 10 sweeps per launch).  Every
+ * schedule gives bitwise identical results. */
 typedef struct {
   int32_t levels;
   float alpha;
@@ -224,7 +225,7 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
  * launches until the next scn_timing_reset).  scn_timing_read synchronises
  * those events and returns the summed duration and launch count of one
  * kernel class ("hist16", "nv12_rgb24", "nv12_resize", "luma_copy",
- * "pyr_down", "hs_warp", "hs_coef", "hs_jacobi", "conv_fwd", "conv_dx",
+ * "pyr_down", "hs_setup", "hs_jacobi", "conv_fwd", "conv_dx",
  * "conv_dw", "flow_up", "gate"); it returns SCN_ENOSPACE if
  * launches were dropped because the pool was full.  Not thread-safe with
  * respect to concurrent enable/reset. */

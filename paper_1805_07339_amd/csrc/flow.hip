@@ -2,7 +2,7 @@
 // consecutive sampled frames -- the FLOW stencil S[0,1] of the Scanner paper
 // (Sec. 3.2, Sec. 5.1.2) -- for gfx950, FP32.
 //
-// Per pair and pyramid level (coarse to fine):
+// Per pair and pyramid level (coarse to fine), in one setup kernel:
 //   warp:  u0, v0 = 2 * bilinear(coarser flow, x/2, y/2) (zero at the coarsest
 //          level); T = bilinear(I2, x + u0, y + v0), coordinates clamped.
 //   coef:  Ix = (Dx I1 + Dx T)/2, Iy likewise (central differences,
@@ -170,57 +170,72 @@ __global__ void __launch_bounds__(kThreads) k_pyr_down(ChunkPtrs c, LevelGeom sr
   c.pyr[f * c.pyr_floats + dst.lvl_off + p] = acc;
 }
 
-// warp: T = I2 sampled at x + start flow.
-__global__ void __launch_bounds__(kThreads) k_hs_warp(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t bpp) {
-  const int64_t pr = blockIdx.x / bpp;
-  const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
-  if (p >= (int64_t)g.w * g.h) return;
+// setup = warp + coef fused on 64 x 16 output tiles: the warped image T, the
+// start flow and I1 of the tile plus a one-pixel clamped halo go to LDS, then
+// the gradients and coefficients use the same expressions as k_hs_warp and
+// k_hs_coef (so the results are bitwise identical) without the T round trip
+// through HBM.
+constexpr int kSetupTW = 64, kSetupTH = 16;
+__global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
+                                                  float alpha2, int32_t tiles_x, int32_t tiles_per_pair) {
+  __shared__ float sT[kSetupTH + 2][kSetupTW + 2];
+  __shared__ float sI[kSetupTH + 2][kSetupTW + 2];
+  __shared__ float sU[kSetupTH][kSetupTW];
+  __shared__ float sV[kSetupTH][kSetupTW];
+  const int64_t pr = blockIdx.x / tiles_per_pair;
   if (c.active && !c.active[pr]) return;
-  const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
-  float u0 = 0.f, v0 = 0.f;
-  if (g.has_coarse) {
-    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
-    start_flow(cu, cu + (int64_t)g.cw * g.ch, g, x, y, &u0, &v0);
-  }
-  const Img i2 = level_img(c, c.pairs[pr].f2, g);
-  plane(c, pr, kPlaneW, g.n0)[p] = warp_sample(i2, g, x, y, u0, v0);
-}
-
-// coef: gradients, linearised constraint and scaled coefficients; writes the
-// start flow into the destination (u, v) buffer.
-__global__ void __launch_bounds__(kThreads) k_hs_coef(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
-                                                      float alpha2, int32_t bpp) {
-  const int64_t pr = blockIdx.x / bpp;
-  const int64_t p = (int64_t)(blockIdx.x % bpp) * kThreads + threadIdx.x;
-  const int64_t n = (int64_t)g.w * g.h;
-  if (p >= n) return;
-  if (c.active && !c.active[pr]) return;
-  const int32_t x = (int32_t)(p % g.w), y = (int32_t)(p / g.w);
-  float u0 = 0.f, v0 = 0.f;
-  if (g.has_coarse) {
-    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
-    start_flow(cu, cu + (int64_t)g.cw * g.ch, g, x, y, &u0, &v0);
-  }
+  const int32_t t = blockIdx.x % tiles_per_pair;
+  const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
   const Img i1 = level_img(c, c.pairs[pr].f1, g);
-  const float* T = plane(c, pr, kPlaneW, g.n0);
-  const int32_t xl = max(x - 1, 0), xr = min(x + 1, g.w - 1);
-  const int32_t yu = max(y - 1, 0), yd = min(y + 1, g.h - 1);
-  const float d1x = (i1.at(xr, y) - i1.at(xl, y)) * 0.5f;
-  const float d1y = (i1.at(x, yd) - i1.at(x, yu)) * 0.5f;
-  const float dTx = (T[(int64_t)y * g.w + xr] - T[(int64_t)y * g.w + xl]) * 0.5f;
-  const float dTy = (T[(int64_t)yd * g.w + x] - T[(int64_t)yu * g.w + x]) * 0.5f;
-  const float Ix = 0.5f * (d1x + dTx);
-  const float Iy = 0.5f * (d1y + dTy);
-  const float It = T[p] - i1.at(x, y);
-  const float Itp = It - Ix * u0 - Iy * v0;
-  const float den = alpha2 + Ix * Ix + Iy * Iy;
-  const float r = 1.0f / sqrtf(den);
-  plane(c, pr, kPlaneA, g.n0)[p] = Ix * r;
-  plane(c, pr, kPlaneB, g.n0)[p] = Iy * r;
-  plane(c, pr, kPlaneC, g.n0)[p] = Itp * r;
+  const Img i2 = level_img(c, c.pairs[pr].f2, g);
+  const float* cu = g.has_coarse ? uv_buf(c, pr, coarse_code, g.n0) : nullptr;
+  const float* cv = cu ? cu + (int64_t)g.cw * g.ch : nullptr;
+  for (int e = threadIdx.x; e < (kSetupTH + 2) * (kSetupTW + 2); e += 256) {
+    const int ty = e / (kSetupTW + 2), tx = e % (kSetupTW + 2);
+    const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
+    float u0 = 0.f, v0 = 0.f;
+    if (cu) start_flow(cu, cv, g, x, y, &u0, &v0);
+    sT[ty][tx] = warp_sample(i2, g, x, y, u0, v0);
+    sI[ty][tx] = i1.at(x, y);
+    const int iy = ty - 1, ix = tx - 1;
+    if (iy >= 0 && iy < kSetupTH && ix >= 0 && ix < kSetupTW) {
+      sU[iy][ix] = u0;
+      sV[iy][ix] = v0;
+    }
+  }
+  __syncthreads();
+  const int64_t n = (int64_t)g.w * g.h;
+  float* pa = plane(c, pr, kPlaneA, g.n0);
+  float* pb = plane(c, pr, kPlaneB, g.n0);
+  float* pc = plane(c, pr, kPlaneC, g.n0);
   float* dst = uv_buf(c, pr, dst_code, g.n0);
-  dst[p] = u0;
-  dst[n + p] = v0;
+  for (int e = threadIdx.x; e < kSetupTH * kSetupTW; e += 256) {
+    const int ly = e / kSetupTW, lx = e % kSetupTW;
+    const int32_t x = ox + lx, y = oy + ly;
+    if (x >= g.w || y >= g.h) continue;
+    const int hx = lx + 1, hy = ly + 1;
+    // clamp-to-edge neighbours: the halo holds the clamped pixels, and at the
+    // image's own border the neighbour index is clamped onto the pixel itself
+    const int xl = (x > 0) ? hx - 1 : hx, xr = (x < g.w - 1) ? hx + 1 : hx;
+    const int yu = (y > 0) ? hy - 1 : hy, yd = (y < g.h - 1) ? hy + 1 : hy;
+    const float u0 = sU[ly][lx], v0 = sV[ly][lx];
+    const float d1x = (sI[hy][xr] - sI[hy][xl]) * 0.5f;
+    const float d1y = (sI[yd][hx] - sI[yu][hx]) * 0.5f;
+    const float dTx = (sT[hy][xr] - sT[hy][xl]) * 0.5f;
+    const float dTy = (sT[yd][hx] - sT[yu][hx]) * 0.5f;
+    const float Ix = 0.5f * (d1x + dTx);
+    const float Iy = 0.5f * (d1y + dTy);
+    const float It = sT[hy][hx] - sI[hy][hx];
+    const float Itp = It - Ix * u0 - Iy * v0;
+    const float den = alpha2 + Ix * Ix + Iy * Iy;
+    const float r = 1.0f / sqrtf(den);
+    const int64_t p = (int64_t)y * g.w + x;
+    pa[p] = Ix * r;
+    pb[p] = Iy * r;
+    pc[p] = Itp * r;
+    dst[p] = u0;
+    dst[n + p] = v0;
+  }
 }
 
 // The per-pixel Jacobi update shared by every Jacobi kernel.
@@ -381,6 +396,146 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming temporally blocked Jacobi ("2.5-D"): one wave owns a strip of 128
+// columns (two per lane, mirrored halo of K columns each side) and a band of
+// rows, and streams down it: each step reads one input row (u, v, a, b, c)
+// and advances every row in flight by one sweep, so that after the step
+// sweep s holds row i - s.  Sweep s keeps its last three rows in VGPRs (the
+// step loop is unrolled by 3 so their slots are static); the coefficients of
+// the K + 1 rows in flight sit in a per-wave LDS ring.  There is no vertical
+// halo tile and no barrier: waves are independent, which lets the loads of
+// one wave overlap the arithmetic of another.  Rows above and below the
+// image are mirrored, which reproduces clamp-to-edge bitwise (same argument
+// as for the tile kernel).  ns <= K sweeps run per launch.
+// One input step of the streaming kernel: input row ii enters sweep 0 and
+// every sweep s <= ns advances row ii - s.  U = ii mod 3 and the sweep index
+// are template parameters so that every window slot is a compile-time
+// register (template recursion instead of a loop the compiler may not unroll).
+template <int K>
+struct StStep {
+  float4 (&win)[K][3];
+  float2 (&ring)[K + 1][3][64];
+  int lane;
+  int32_t ns, y0, y1, w;
+  float* du;
+  float* dv;
+  int32_t cx0, cx1;
+  bool in0, in1;
+
+  template <int U, int S>
+  __device__ __forceinline__ void sweep(int32_t ii) {
+    if constexpr (S <= K) {
+      if (S > ns) return;
+      constexpr int RING = K + 1;
+      const float4 A = win[S - 1][(U - S + 2 + 3 * K) % 3];
+      const float4 B = win[S - 1][(U - S + 3 * K) % 3];
+      const float4 C = win[S - 1][(U - S + 1 + 3 * K) % 3];
+      const int rr = (((ii - S) % RING) + RING) % RING;
+      const float2 ca = ring[rr][0][lane];
+      const float2 cb = ring[rr][1][lane];
+      const float2 cc = ring[rr][2][lane];
+      const float qu0 = A.x + C.x, qu1 = A.y + C.y, qv0 = A.z + C.z, qv1 = A.w + C.w;
+      const float cu0 = fmaf(B.x, 2.f, qu0), cu1 = fmaf(B.y, 2.f, qu1);
+      const float cv0 = fmaf(B.z, 2.f, qv0), cv1 = fmaf(B.w, 2.f, qv1);
+      const float ub0 = jac_bar(qu0, dpp_from_left(cu1), cu1);
+      const float ub1 = jac_bar(qu1, cu0, dpp_from_right(cu0));
+      const float vb0 = jac_bar(qv0, dpp_from_left(cv1), cv1);
+      const float vb1 = jac_bar(qv1, cv0, dpp_from_right(cv0));
+      float4 N;
+      jac_update(ub0, vb0, ca.x, cb.x, cc.x, &N.x, &N.z);
+      jac_update(ub1, vb1, ca.y, cb.y, cc.y, &N.y, &N.w);
+      if constexpr (S < K) win[S][(U - S + 3 * K) % 3] = N;
+      if (S == ns) {
+        const int32_t r = ii - S;
+        if (r >= y0 && r < y1) {
+          const int64_t o = (int64_t)r * w;
+          if (in0) {
+            du[o + cx0] = N.x;
+            dv[o + cx0] = N.z;
+          }
+          if (in1) {
+            du[o + cx1] = N.y;
+            dv[o + cx1] = N.w;
+          }
+        }
+        return;
+      }
+      sweep<U, S + 1>(ii);
+    }
+  }
+
+  template <int U, typename F>
+  __device__ __forceinline__ void step(int32_t ii, float4& nuv, float2& na, float2& nb, float2& nc, F&& load_row) {
+    constexpr int RING = K + 1;
+    win[0][U] = nuv;
+    const int rs = ((ii % RING) + RING) % RING;
+    ring[rs][0][lane] = na;
+    ring[rs][1][lane] = nb;
+    ring[rs][2][lane] = nc;
+    load_row(ii + 1);
+    sweep<U, 1>(ii);
+  }
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
+                                                      int32_t ns, int32_t strips, int32_t bands, int32_t band_h) {
+  constexpr int RING = K + 1;
+  __shared__ float2 ring[4][RING][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t unit = (int64_t)blockIdx.x * 4 + wv;          // (pair, band, strip)
+  const int64_t per_pair = (int64_t)strips * bands;
+  const int64_t pr = unit / per_pair;
+  if (pr >= c.n_pairs) return;
+  if (c.active && !c.active[pr]) return;
+  const int32_t rem = (int32_t)(unit % per_pair);
+  const int32_t band = rem / strips, strip = rem % strips;
+  const int32_t ox = strip * (128 - 2 * K) - K;
+  const int32_t y0 = band * band_h, y1 = min(g.h, y0 + band_h);
+  const int64_t n = (int64_t)g.w * g.h;
+  const float* su = uv_buf(c, pr, src_code, g.n0);
+  const float* sv = su + n;
+  const float* pa = plane(c, pr, kPlaneA, g.n0);
+  const float* pb = plane(c, pr, kPlaneB, g.n0);
+  const float* pc = plane(c, pr, kPlaneC, g.n0);
+  float* du = uv_buf(c, pr, dst_code, g.n0);
+  float* dv = du + n;
+  const int32_t cx0 = ox + 2 * lane, cx1 = cx0 + 1;
+  const int32_t gx0 = reflect(cx0, g.w), gx1 = reflect(cx1, g.w);
+  const bool in0 = (cx0 >= ox + K) && (cx0 < ox + 128 - K) && (cx0 < g.w);
+  const bool in1 = (cx1 >= ox + K) && (cx1 < ox + 128 - K) && (cx1 < g.w);
+
+  // sweep windows: win[s][slot] = (u col0, u col1, v col0, v col1) of sweep s's row with row % 3 == slot
+  float4 win[K][3];
+#pragma unroll
+  for (int s = 0; s < K; ++s)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) win[s][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  int32_t i = y0 - K - 1;
+  i -= ((i % 3) + 3) % 3;  // start on a multiple of 3 so that slots are static
+  const int32_t i_end = y1 - 1 + ns;
+  // prefetch of input row i
+  float4 nuv;
+  float2 na, nb, nc;
+  auto load_row = [&](int32_t row) {
+    const int64_t r = (int64_t)reflect(row, g.h) * g.w;
+    nuv = make_float4(su[r + gx0], su[r + gx1], sv[r + gx0], sv[r + gx1]);
+    na = make_float2(pa[r + gx0], pa[r + gx1]);
+    nb = make_float2(pb[r + gx0], pb[r + gx1]);
+    nc = make_float2(pc[r + gx0], pc[r + gx1]);
+  };
+  load_row(i);
+  StStep<K> st{win, ring[wv], lane, ns, y0, y1, g.w, du, dv, cx0, cx1, in0, in1};
+  for (; i <= i_end; i += 3) {
+    st.template step<0>(i, nuv, na, nb, nc, load_row);
+    st.template step<1>(i + 1, nuv, na, nb, nc, load_row);
+    st.template step<2>(i + 2, nuv, na, nb, nc, load_row);
+  }
+}
+
 LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
   LevelGeom g;
   g.w = grp.dims[l].w;
@@ -399,9 +554,10 @@ LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
 // Jacobi kernel variants: (rows per wave, waves per workgroup); variant 0 is
 // the one-sweep reference kernel.
 struct JacobiVariant {
-  int32_t rows, waves;
+  int32_t rows, waves;  // tile variants; streaming variants use rows = 0 and waves = K
 };
-constexpr JacobiVariant kVariants[] = {{1, 4}, {8, 16}, {16, 8}, {8, 8}, {4, 16}};
+constexpr JacobiVariant kVariants[] = {{1, 4}, {8, 16}, {16, 8}, {8, 8}, {4, 16}, {0, 6}, {0, 8}, {0, 10}};
+constexpr int kBandRows = 256;  // rows per streaming band
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct JacobiChoice {
@@ -411,6 +567,8 @@ struct JacobiChoice {
 
 bool variant_fits(int v, int32_t k, const LevelGeom& g) {
   if (v == 0) return k == 1;
+  if (kVariants[v].rows == 0) return k >= 1 && k <= kVariants[v].waves && kVariants[v].waves <= g.w &&
+                                     kVariants[v].waves + 4 <= g.h;
   const int32_t th = kVariants[v].rows * kVariants[v].waves;
   return k >= 1 && 2 * k < 128 && 2 * k < th && k <= g.w && k <= g.h;
 }
@@ -430,6 +588,23 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     return SCN_OK;
   }
   const JacobiVariant v = kVariants[jc.variant];
+  if (v.rows == 0) {
+    const int32_t K = v.waves;
+    const int32_t strips = (g.w + (128 - 2 * K) - 1) / (128 - 2 * K);
+    const int32_t bands = (g.h + kBandRows - 1) / kBandRows;
+    const int32_t band_h = (g.h + bands - 1) / bands;
+    const int64_t units = (int64_t)strips * bands * n_pairs;
+    const int64_t grid = (units + 3) / 4;
+    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    switch (K) {
+      case 6: hipLaunchKernelGGL((k_hs_jacobi_st<6>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
+      case 8: hipLaunchKernelGGL((k_hs_jacobi_st<8>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
+      case 10: hipLaunchKernelGGL((k_hs_jacobi_st<10>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
+      default: set_error("internal: bad streaming Jacobi variant"); return SCN_EINVAL;
+    }
+    SCN_LAUNCHED("jacobi launch");
+    return SCN_OK;
+  }
   const int32_t th = v.rows * v.waves;
   const int32_t tiles_x = (g.w + (128 - 2 * jc.k) - 1) / (128 - 2 * jc.k);
   const int32_t tiles_y = (g.h + (th - 2 * jc.k) - 1) / (th - 2 * jc.k);
@@ -496,18 +671,16 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     const int32_t coarse = result < 0 ? 0 : result;
     const int32_t x = result < 0 ? 0 : 1 - result;
-    {
-      KernelTimer timer("hs_warp", s);
-      hipLaunchKernelGGL(k_hs_warp, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, (int32_t)bpp);
-    }
-    SCN_LAUNCHED("warp launch");
     const int32_t start_dst = (l == 0 && prm.iters == 0) ? 2 : x;
     {
-      KernelTimer timer("hs_coef", s);
-      hipLaunchKernelGGL(k_hs_coef, dim3((unsigned)grid), dim3(kThreads), 0, s, c, g, coarse, start_dst, alpha2,
-                         (int32_t)bpp);
+      const int32_t tiles_x = (g.w + kSetupTW - 1) / kSetupTW, tiles_y = (g.h + kSetupTH - 1) / kSetupTH;
+      const int64_t tpp = (int64_t)tiles_x * tiles_y;
+      if (tpp * ch.n_pairs > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+      KernelTimer timer("hs_setup", s);
+      hipLaunchKernelGGL(k_hs_setup, dim3((unsigned)(tpp * ch.n_pairs)), dim3(256), 0, s, c, g, coarse, start_dst,
+                         alpha2, tiles_x, (int32_t)tpp);
     }
-    SCN_LAUNCHED("coef launch");
+    SCN_LAUNCHED("setup launch");
     int32_t cur = start_dst;
     if (prm.iters > 0) {
       const JacobiChoice jc = choose_jacobi(grp, l, ch.n_pairs, prm, c, g, cur, s);

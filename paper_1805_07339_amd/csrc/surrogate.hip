@@ -149,6 +149,92 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
   }
 }
 
+// Forward convolution with the input tile in LDS: a workgroup owns TOH x TOW
+// output pixels of one image; the (TOH-1)S+3 x (TOW-1)S+3 effective input
+// pixels it reads (zero outside the image, nearest-upsampled for x2 layers)
+// are loaded once with 16-byte loads into LDS (channel stride padded by 8 to
+// spread banks), and all nine taps read their A fragments from there, so each
+// input element crosses the memory hierarchy once per workgroup instead of
+// nine times.  Each wave owns 16 * MR output pixels (MR pixel blocks of 16
+// along a row) x all output channels.
+template <int L, int TOH, int TOW>
+__global__ void __launch_bounds__(256) k_conv_fwd_lds(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
+                                                      void* __restrict__ y, CGeom g, int32_t tiles_x,
+                                                      int32_t tiles_per_img) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16;
+  constexpr bool UP = D.up != 0, RELU = D.relu != 0;
+  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / 4;
+  static_assert(CI % 32 == 0 && TOW % 16 == 0 && NBLK % 4 == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
+  const bf16_t* wf = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
+  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int n = blockIdx.x / tiles_per_img;
+  const int t = blockIdx.x % tiles_per_img;
+  const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
+  const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
+  for (int e = tid; e < IH * IW * (CI / 8); e += 256) {
+    const int ch = e % (CI / 8), p = e / (CI / 8);
+    const int py = p / IW, px = p % IW;
+    const int iy = iy0 + py, ix = ix0 + px;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
+      const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+      v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
+    }
+    *reinterpret_cast<uint4*>(tile + (py * IW + px) * CP + ch * 8) = v;
+  }
+  __syncthreads();
+  f32x4 acc[MR][NB];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+    for (int cb = 0; cb < CI / 32; ++cb) {
+      bf16x8 a[MR];
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        const int blk = wv * MR + mr;
+        const int orow = blk / BPR, ocol = (blk % BPR) * 16 + r16;
+        a[mr] = ld8(tile + ((orow * S + ky) * IW + ocol * S + kx) * CP + cb * 32 + kg * 8);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 b = ld8(wf + ((int64_t)(tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8));
+#pragma unroll
+        for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+      }
+    }
+  }
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr) {
+    const int blk = wv * MR + mr;
+    const int oy = oy0 + blk / BPR;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = nb * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ox = ox0 + (blk % BPR) * 16 + kg * 4 + i;
+        if (oy >= g.ho || ox >= g.wo || co >= CO) continue;
+        const int64_t m = ((int64_t)n * g.ho + oy) * g.wo + ox;
+        float v = acc[mr][nb][i] + bias[co];
+        if (RELU) v = fmaxf(v, 0.f);
+        if constexpr (L == kLayers - 1)
+          reinterpret_cast<float*>(y)[m * CO + co] = v;
+        else
+          reinterpret_cast<bf16_t*>(y)[m * CO + co] = f2bf(v);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // input gradient of the effective input: dxe[m][ci] = sum_{tap, co} W[tap][co][ci] dy(out(m, tap))[co]
 template <int L, int MR>
@@ -740,13 +826,25 @@ CGeom layer_geom(const NetDims& d, int l, int64_t n) {
 
 constexpr int kMR = 2;  // 16-pixel row blocks per wave
 
+// Output tile (rows x columns) of the LDS-tiled forward kernel per layer.
+template <int L> struct FwdTile { static constexpr int TOH = kNet[L].stride == 2 ? 4 : 8, TOW = 32; };
+
 template <int L>
 scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom& g, hipStream_t s) {
-  const int64_t M = (int64_t)g.n * g.ho * g.wo;
-  const int64_t per_wg = 4 * 16 * kMR;
-  const int64_t grid = (M + per_wg - 1) / per_wg;
   KernelTimer timer("conv_fwd", s);
-  hipLaunchKernelGGL((k_conv_fwd<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g);
+  if constexpr (L == 0) {  // 2 input channels: K = 18 fits one MFMA K block, no tiling needed
+    const int64_t M = (int64_t)g.n * g.ho * g.wo;
+    const int64_t per_wg = 4 * 16 * kMR;
+    const int64_t grid = (M + per_wg - 1) / per_wg;
+    hipLaunchKernelGGL((k_conv_fwd<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g);
+  } else {
+    constexpr int TOH = FwdTile<L>::TOH, TOW = FwdTile<L>::TOW;
+    const int32_t tx = (g.wo + TOW - 1) / TOW, ty = (g.ho + TOH - 1) / TOH;
+    const int64_t grid = (int64_t)tx * ty * g.n;
+    if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+    hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g, tx,
+                       tx * ty);
+  }
   SCN_LAUNCHED("conv forward launch");
   return SCN_OK;
 }
