@@ -120,6 +120,13 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     conv_ms, conv_n = scn.timing_read("conv_fwd")
+    per_layer = {}
+    for li in range(1, 7):
+        ms, _ = scn.timing_read("conv_fwd%d" % li)
+        per_layer["conv%d" % li] = ms / args.steps
+    gate_ms, _ = scn.timing_read("gate")
+    up_ms, _ = scn.timing_read("flow_up")
+    fb_ms = {k: scn.timing_read(k)[0] / args.steps for k in ["pyr_down", "hs_setup", "hs_jacobi"]}
     scn.timing_enable(False)
     n_pairs = sum(f.shape[0] for f in plain_flows)
     epe = torch.cat([torch.sqrt(((o - p) ** 2).sum(dim=1)).mean(dim=(1, 2)) for o, p in zip(outs, plain_flows)])
@@ -132,13 +139,287 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     return {"value": m_total * args.steps / dt, "unit": "frames/s", "ms_per_step": dt / args.steps * 1e3,
             "tau": tau, "fallback_rate": float(fb.mean()), "mean_epe_vs_plain_px": float(epe.mean()),
             "max_pair_epe_px": float(epe.max()), "network_only_mean_epe_px": float(epe_net.mean()),
+            "ms_per_step_by_kernel": {**per_layer, "gate": gate_ms / args.steps, "flow_up": up_ms / args.steps,
+                                      **{"fallback_" + k: v for k, v in fb_ms.items()}},
             "mfma": {"achieved_TFLOPs": mfma_tflops, "peak_TFLOPs": BF16_PEAK_TFLOPS,
                      "utilisation": mfma_tflops / BF16_PEAK_TFLOPS, "conv_fwd_ms": conv_ms,
                      "flop_per_1080p_pair": _conv_flops(W, H)},
             "weights": os.path.relpath(path, ROOT), "train_meta": {k: meta[k] for k in meta if k != "loss_history"}}
 
 
+# ---------------------------------------------------------------------------
+# extra workloads (own JSON line with --workload): uneven multi-stream flow and
+# a camera rig
+
+C3_RES = [(640, 360), (1280, 720), (1920, 1080), (3840, 2160)]
+C3_STREAMS_PER_RES, C3_ROWS, C3_WINDOW = 16, 2400, 240
+
+
+def _px_levels(w, h, levels):
+    from oracle.hs import level_sizes
+    return sum(a * b for a, b in level_sizes(w, h, levels))
+
+
+def _timed_calls(torch, calls, steps, warmup):
+    for _ in range(warmup):
+        for c in calls:
+            c()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in calls:
+            c()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def c3_workload(scn, torch, dev, args):
+    """64 streams (16 each at 360p, 720p, 1080p, 4K), one seeded 240-row RANGE
+    window per stream in a 2400-row table; only window rows are resident.
+    Flow of all 15,296 pairs, batched as 4 calls of 16 jobs (4 per resolution)
+    whose outputs reuse one ring of buffers; then per-resolution calls."""
+    import synth
+    stream = torch.cuda.current_stream()
+    prm = scn.flow_params(LEVELS, ALPHA, ITERS)
+    t_gen = time.perf_counter()
+    jobs = {}  # (res index, k) -> job
+    keep = []
+    for r, (w, h) in enumerate(C3_RES):
+        for k in range(C3_STREAMS_PER_RES):
+            seed = 3000 + r * C3_STREAMS_PER_RES + k
+            (b, e), = synth.range_windows(seed, C3_ROWS, C3_WINDOW)
+            scene = synth.layered_scene(seed, w, h)
+            rows = torch.empty((e - b, w * h * 3 // 2), dtype=torch.uint8, device=dev)
+            bs = max(1, min(16, (1 << 23) // (w * h) * 4))
+            for q in range(0, e - b, bs):
+                ts = list(range(b + q, min(e, b + q + bs)))
+                rows[q:q + len(ts)] = synth.scene_batch_nv12(scene, ts, dev).reshape(len(ts), -1)
+            keep.append(rows)
+            tab = scn.Table.window(rows, b, C3_ROWS, w, h)
+            jobs[(r, k)] = scn.Job(tab, scn.Sampling.range([(b, e)]))
+        print("c3: generated %dx%d streams (%.0f s)" % (w, h, time.perf_counter() - t_gen), file=sys.stderr,
+              flush=True)
+    gen_s = time.perf_counter() - t_gen
+    resident_gb = sum(t.numel() for t in keep) / 1e9
+    per_call = C3_STREAMS_PER_RES // 4
+    mixed = [[jobs[(r, 4 * q + i)] for r in range(len(C3_RES)) for i in range(per_call)] for q in range(4)]
+    ring = [torch.empty((scn.count_pairs(j), 2, j.table.height, j.table.width), dtype=torch.float32, device=dev)
+            for j in mixed[0]]
+    ws_bytes = int(args.c3_ws_gb * (1 << 30))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    def _call(js, slots):
+        outs = [ring[k] for k in slots]
+        return lambda: scn.flow(js, prm, outs=outs, stream=stream, ws=ws, ws_bytes=ws_bytes)
+
+    # ring slot r * per_call + i holds the output of the i-th resolution-r job of a call
+    calls = [_call(js, range(len(js))) for js in mixed]
+    scn.timing_enable(True, 1 << 20)
+    scn.timing_reset()
+    dt = _timed_calls(torch, calls, args.steps, args.warmup)
+    jac_ms, jac_n = scn.timing_read("hs_jacobi")
+    scn.timing_enable(False)
+    frames = sum(scn.count_rows(j) for j in jobs.values())
+    pairs = sum(scn.count_pairs(j) for j in jobs.values())
+    px_sweeps = sum(scn.count_pairs(j) * _px_levels(j.table.width, j.table.height, LEVELS)
+                    for j in jobs.values()) * ITERS
+    jac_steps = args.steps + args.warmup
+    per_res = {}
+    for r, (w, h) in enumerate(C3_RES):
+        rc = [_call([jobs[(r, 4 * q + i)] for i in range(per_call)], [r * per_call + i for i in range(per_call)])
+              for q in range(4)]
+        t = _timed_calls(torch, rc, 1, 1)
+        fr = sum(scn.count_rows(jobs[(r, k)]) for k in range(C3_STREAMS_PER_RES))
+        pr = sum(scn.count_pairs(jobs[(r, k)]) for k in range(C3_STREAMS_PER_RES))
+        per_res["%dx%d" % (w, h)] = {"frames_per_s": fr / t, "pairs_per_s": pr / t, "s_per_pass": t}
+    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * jac_steps / (jac_ms * 1e-3) / 1e12
+    return {"metric": "frames/s through flow, 64 uneven streams (C3)", "value": frames / dt, "unit": "frames/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 streams: 16 each at 640x360, 1280x720, 1920x1080, 3840x2160; one 240-row "
+                                   "RANGE window per stream (seeds 3000+s) in a 2400-row table; Horn-Schunck "
+                                   "L=%d alpha=%g %d iters; 4 batched calls of 16 mixed-resolution jobs per step"
+                                   % (LEVELS, ALPHA, ITERS),
+                       "frames_per_step": frames, "pairs_per_step": pairs, "resident_nv12_GB": resident_gb,
+                       "workspace_GB": ws_bytes / 2 ** 30, "generation_s": gen_s},
+            "pairs_per_s": pairs / dt,
+            "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None},
+            "per_resolution": per_res}
+
+
+def c5_workload(scn, torch, dev, args):
+    """Camera rig: 14 cameras x 300 time steps at 2048x2048 (rows t*14 + c), flow
+    of the 13 neighbouring-camera pairs per time step (RANGE windows of 14 rows),
+    5 levels; 3,900 pairs, batched as calls of 60 time steps (780 pairs) that
+    reuse one output ring."""
+    import synth
+    cams, steps_t, S = 14, 300, 2048
+    levels = 5
+    stream = torch.cuda.current_stream()
+    prm = scn.flow_params(levels, ALPHA, ITERS)
+    t_gen = time.perf_counter()
+    rig = synth.rig_scene(5, S, S, cams)
+    rows = torch.empty((cams * steps_t, S * S * 3 // 2), dtype=torch.uint8, device=dev)
+    for t in range(steps_t):
+        rows[t * cams:(t + 1) * cams] = synth.rig_batch_nv12(rig, [(c, t) for c in range(cams)], dev).reshape(cams, -1)
+    gen_s = time.perf_counter() - t_gen
+    print("c5: generated rig (%.0f s)" % gen_s, file=sys.stderr, flush=True)
+    tab = scn.Table.from_tensor(rows, S, S)
+    per_call_t = 60
+    jobs = [scn.Job(tab, scn.Sampling.range([(t * cams, (t + 1) * cams) for t in range(t0, t0 + per_call_t)]))
+            for t0 in range(0, steps_t, per_call_t)]
+    ring = torch.empty((scn.count_pairs(jobs[0]), 2, S, S), dtype=torch.float32, device=dev)
+    ws_bytes = int(args.c3_ws_gb * (1 << 30))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    calls = [(lambda j=j: scn.flow([j], prm, outs=[ring], stream=stream, ws=ws, ws_bytes=ws_bytes)) for j in jobs]
+    scn.timing_enable(True, 1 << 20)
+    scn.timing_reset()
+    dt = _timed_calls(torch, calls, args.steps, args.warmup)
+    jac_ms, _ = scn.timing_read("hs_jacobi")
+    scn.timing_enable(False)
+    pairs = sum(scn.count_pairs(j) for j in jobs)
+    frames = cams * steps_t
+    px_sweeps = pairs * _px_levels(S, S, levels) * ITERS
+    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * (args.steps + args.warmup) / (jac_ms * 1e-3) / 1e12
+    return {"metric": "rig frames/s through flow (C5)", "value": frames / dt, "unit": "frames/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "14-camera rig x 300 steps at 2048x2048, 13 chain pairs per step (RANGE "
+                                   "windows of 14 rows), Horn-Schunck L=5 alpha=%g %d iters; 5 calls of 780 "
+                                   "pairs per step" % (ALPHA, ITERS),
+                       "frames_per_step": frames, "pairs_per_step": pairs, "resident_nv12_GB": rows.numel() / 1e9,
+                       "workspace_GB": ws_bytes / 2 ** 30, "generation_s": gen_s},
+            "pairs_per_s": pairs / dt,
+            "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None}}
+
+
+def summarize_rocprof(directory: str) -> str:
+    """Short text summary of rocprofv3 CSV output (kernel stats of this library's
+    kernels, and per-kernel sums of any collected counters)."""
+    import csv
+    import glob
+    out = []
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "").replace("void ", "")
+        return n.split("(")[0]
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
+        out.append("# kernel stats: %s" % os.path.relpath(f, directory))
+        out.append("%-48s %8s %14s %12s %7s" % ("kernel", "calls", "total_ns", "avg_ns", "pct"))
+        for r in csv.DictReader(open(f)):
+            if "scn::" not in r["Name"] and "copy" not in r["Name"].lower():
+                continue
+            out.append("%-48s %8s %14.0f %12.1f %7.2f" % (short(r["Name"])[:48], r["Calls"], float(r["TotalDurationNs"]),
+                                                          float(r["AverageNs"]), float(r["Percentage"])))
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        agg = {}
+        for r in csv.DictReader(open(f)):
+            name = r.get("Kernel_Name", "")
+            if "scn::" not in name and "copy" not in name.lower():
+                continue
+            key = (short(name)[:48], r.get("Counter_Name", ""))
+            tot, n, mx = agg.get(key, (0.0, 0, 0.0))
+            v = float(r.get("Counter_Value", 0) or 0)
+            agg[key] = (tot + v, n + 1, max(mx, v))
+        out.append("# counters: %s (per-dispatch values summed over the dispatches of each kernel)" %
+                   os.path.relpath(f, directory))
+        out.append("%-48s %-12s %10s %16s %16s %16s" % ("kernel", "counter", "dispatches", "sum", "mean", "max"))
+        for (k, c), (tot, n, mx) in sorted(agg.items()):
+            out.append("%-48s %-12s %10d %16.1f %16.1f %16.1f" % (k, c, n, tot, tot / n, mx))
+    return "\n".join(out)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hs_jacobi_traffic_1080p_stride24_gather1.txt")
+
+
+def _flow_source_hash() -> str:
+    """sha256 of the Jacobi kernels' source (the counters describe this code)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("flow.hip", "tune.inc"):
+        with open(os.path.join(ROOT, "paper_1805_07339_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
+    """HBM bytes of the timed step's Jacobi launches from two counter runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the 1 GiB device copy of the run (--calib-copy)."""
+    import csv
+    import glob
+
+    def rows(d):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for k, r in enumerate(csv.DictReader(open(f))):
+                did = r.get("Dispatch_Id") or r.get("Dispatch_ID") or r.get("Correlation_Id")
+                out.append((int(did) if did else k, r.get("Kernel_Name", ""),
+                            float(r.get("Counter_Value", 0) or 0)))
+        # one value per dispatch (sum over instances / dimensions)
+        agg = {}
+        for i, name, v in out:
+            n, t = agg.get(i, (name, 0.0))
+            agg[i] = (n, t + v)
+        return sorted((i, n, v) for i, (n, v) in agg.items())
+
+    info = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    n_launch = int(info["roofline"]["launches"])
+    res = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rs = rows(d)
+        copy = max(v for _, n, v in rs if "copyBuffer" in n)
+        factor = (1 << 30) / 1024.0 / copy  # KiB a 1 GiB copy must move per direction, over what was read
+        jac = [v for _, n, v in rs if "k_hs_jacobi" in n][-n_launch:]
+        res[ctr] = (factor, copy, sum(jac) * 1024.0 * factor, len(jac))
+    fb, wb = res["FETCH_SIZE"][2], res["WRITE_SIZE"][2]
+    alg = info["roofline"]["px_sweeps"] * 28.0
+    lines = [
+        "# HBM traffic of the Jacobi launches of one timed step (1080p STRIDE-24 + GATHER 1%%, %d pairs)"
+        % info["config"]["pairs_per_step"],
+        "# source sha256(flow.hip + tune.inc) = %s" % _flow_source_hash(),
+        "# commands (from the repository root, cd /tmp && export TMPDIR=/tmp first):",
+        "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o run -- python3 bench.py --steps 1 --warmup 1 "
+        "--no-cpu-baseline --no-surrogate --calib-copy",
+        "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o run -- python3 bench.py (same arguments)",
+        "#   python3 bench.py --traffic-summary <F> <W> <bench json of the FETCH run>",
+        "# copy calibration (1 GiB device copy): FETCH_SIZE %.1f KiB -> factor %.4f; WRITE_SIZE %.1f KiB -> factor %.4f"
+        % (res["FETCH_SIZE"][1], res["FETCH_SIZE"][0], res["WRITE_SIZE"][1], res["WRITE_SIZE"][0]),
+        "jacobi_launches_per_step %d" % n_launch,
+        "fetch_bytes_per_step %.0f" % fb,
+        "write_bytes_per_step %.0f" % wb,
+        "traffic_bytes_per_launch %.0f" % ((fb + wb) / n_launch),
+        "streaming_algorithmic_bytes_per_step %.0f  (28 B per pixel-sweep)" % alg,
+        "traffic_over_streaming_algorithmic %.4f" % ((fb + wb) / alg),
+    ]
+    return "\n".join(lines)
+
+
+def read_traffic():
+    """Measured HBM bytes per Jacobi launch, if the committed counter summary
+    describes the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None, "no counter summary"
+    kv = {}
+    src = None
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("# source sha256"):
+            src = line.split("=")[-1].strip()
+        elif not line.startswith("#") and line.strip():
+            k, v = line.split()[:2]
+            kv[k] = float(v)
+    if src != _flow_source_hash():
+        return None, "counter summary predates the current Jacobi source"
+    return kv.get("traffic_bytes_per_launch"), os.path.relpath(TRAFFIC_PROFILE, ROOT)
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
+        print(summarize_rocprof(sys.argv[2]))
+        return
+    if len(sys.argv) > 4 and sys.argv[1] == "--traffic-summary":
+        print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -148,6 +429,12 @@ def main():
     ap.add_argument("--sweeps-per-pass", type=int, default=0)
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--tau", type=float, default=None, help="gate threshold (default: the calibrated one)")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2",
+                    help="c2: the 1080p sampled-stream step (default); c3: 64 uneven streams; c5: camera rig")
+    ap.add_argument("--c3-ws-gb", type=float, default=32.0, help="flow workspace for --workload c3/c5 (GiB)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the pixel stage has no multi-GPU path "
@@ -164,6 +451,10 @@ def main():
     torch.cuda.set_device(dev)
     os.environ.setdefault("SCN_TUNE_CACHE", os.path.join(ROOT, "gpurun_out", "scn_tune.txt")
                           if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else "/tmp/scn_tune.txt")
+    if args.workload != "c2":
+        fn = c3_workload if args.workload == "c3" else c5_workload
+        print(json.dumps(fn(scn, torch, dev, args)))
+        return
     # --- synthetic input, resident in HBM ---------------------------------
     stride_rows = OS.rows("stride", N_ROWS, start=0, step=24, stop=N_ROWS)
     gather_rows = synth.gather_list(2, N_ROWS, 0.01)
@@ -204,10 +495,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
-    kern = {k: scn.timing_read(k) for k in ["hist16", "pyr_down", "hs_setup", "hs_jacobi"]}
+    kern = {k: scn.timing_read(k) for k in ["hist16", "pyr_down", "hs_setup", "hs_jacobi"] +
+            ["hs_jacobi_l%d" % l for l in range(LEVELS)]}
     scn.timing_enable(False)
 
     # --- algorithmic work of the dominant kernel (Jacobi) -------------------
+    traffic, traffic_src = read_traffic()
     from oracle.hs import level_sizes
     lv = level_sizes(W, H, LEVELS)
     px_levels = sum(w * h for w, h in lv)
@@ -241,7 +534,14 @@ def main():
     conv_gbs = 4.5 * W * H * 400 * conv_n / (conv_ms * 1e-3) / 1e9
     del big, rgb
 
-    surrogate = surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args)
+    surrogate = (None if args.no_surrogate else
+                 surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     result = {
         "metric": "1080p frames/s (HIST+flow), surrogate vs plain at EPE<=0.5px; % HBM roofline",
@@ -261,7 +561,9 @@ def main():
                                "%d iters" % (LEVELS, ALPHA, ITERS),
                    "frames_per_step": m_total, "pairs_per_step": p_total, "width": W, "height": H},
         "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src,
                      "launches": jac_n, "avg_launch_ms": jac_ms / max(jac_n, 1),
                      "flop_per_px_sweep": FLOP_PER_PX_SWEEP, "px_sweeps": px_sweeps,
                      "streaming_equivalent_GBps": jac_stream_gbs,

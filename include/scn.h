@@ -65,7 +65,9 @@ typedef enum {
  * of pitch bytes, the first width bytes used) followed by the interleaved
  * chroma plane (height/2 rows of pitch bytes: U0 V0 U1 V1 ...).
  * width and height are even and >= 2; pitch >= width;
- * frame_bytes >= pitch * height * 3 / 2. */
+ * frame_bytes >= pitch * height * 3 / 2.
+ * Only the rows a call samples are read, so only those rows need to be backed
+ * by memory (a table may be a view of which a window of rows is resident). */
 typedef struct {
   const uint8_t* frames; /* device */
   int32_t width, height, pitch, reserved;
@@ -226,7 +228,9 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
  * those events and returns the summed duration and launch count of one
  * kernel class ("hist16", "nv12_rgb24", "nv12_resize", "luma_copy",
  * "pyr_down", "hs_setup", "hs_jacobi", "conv_fwd", "conv_dx",
- * "conv_dw", "flow_up", "gate"); it returns SCN_ENOSPACE if
+ * "conv_dw", "flow_up", "gate"), or of a finer class ("hs_jacobi_l0" ..
+ * "hs_jacobi_l6" per pyramid level, "conv_fwd1" .. "conv_fwd6" per layer);
+ * nested classes time the same launches.  It returns SCN_ENOSPACE if
  * launches were dropped because the pool was full.  Not thread-safe with
  * respect to concurrent enable/reset. */
 scn_status scn_timing_enable(int32_t enable, int32_t max_launches);

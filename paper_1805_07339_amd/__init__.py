@@ -151,6 +151,21 @@ class Table:
     pitch: int
     frame_bytes: int
     n_frames: int
+    row0: int = 0  # table row held by frames[0] (window views)
+
+    @staticmethod
+    def window(rows: torch.Tensor, first_row: int, n_frames: int, width: int, height: int,
+               pitch: Optional[int] = None) -> "Table":
+        """A table of n_frames rows of which only rows first_row .. first_row +
+        len(rows) - 1 are backed by memory (rows[i] holds row first_row + i).
+        Only sampled rows are ever read, so a job may use such a view as long as
+        its sampling stays inside the backed rows (Sec. 4.2: frames that no
+        output needs are never materialised)."""
+        t = Table.from_tensor(rows, width, height, pitch)
+        if first_row < 0 or first_row + t.n_frames > n_frames:
+            raise ValueError("window rows fall outside the table")
+        t.row0, t.n_frames = first_row, n_frames
+        return t
 
     @staticmethod
     def from_tensor(frames: torch.Tensor, width: int, height: int, pitch: Optional[int] = None) -> "Table":
@@ -162,8 +177,8 @@ class Table:
         return Table(frames, width, height, pitch, fb, n)
 
     def c(self) -> CTable:
-        return CTable(self.frames.data_ptr(), self.width, self.height, self.pitch, 0, self.frame_bytes,
-                      self.n_frames)
+        return CTable(self.frames.data_ptr() - self.row0 * self.frame_bytes, self.width, self.height, self.pitch, 0,
+                      self.frame_bytes, self.n_frames)
 
 
 class Sampling:

@@ -125,14 +125,6 @@ __device__ __forceinline__ void start_flow(const float* cu, const float* cv, con
   *v0 = 2.f * bilinear_split(atv, g.cw, g.ch, xi, xf, yi, yf);
 }
 
-__device__ __forceinline__ float warp_sample(const Img& im, const LevelGeom& g, int32_t x, int32_t y, float u0, float v0) {
-  const float fu = floorf(u0), fv = floorf(v0);
-  const int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
-  const float xf = u0 - fu, yf = v0 - fv;
-  auto at = [&](int32_t xx, int32_t yy) { return im.at(xx, yy); };
-  return bilinear_split(at, g.w, g.h, xi, xf, yi, yf);
-}
-
 // ---------------------------------------------------------------------------
 // pyramid: level l = even samples of blur5(level l-1), [1,4,6,4,1]/16
 // horizontal then vertical, clamp-to-edge.  One thread per output pixel.
@@ -176,8 +168,14 @@ __global__ void __launch_bounds__(kThreads) k_pyr_down(ChunkPtrs c, LevelGeom sr
 // k_hs_coef (so the results are bitwise identical) without the T round trip
 // through HBM.
 constexpr int kSetupTW = 64, kSetupTH = 16;
+// U8: level 0 (luma read as u8 from the table); COARSE: a coarser level
+// exists (start flow from it).  Each thread gathers all of its halo-tile
+// samples into registers before the first LDS store, so the loads of one
+// thread overlap instead of waiting one by one.
+template <bool U8, bool COARSE>
 __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
                                                   float alpha2, int32_t tiles_x, int32_t tiles_per_pair) {
+  constexpr int TW = kSetupTW + 2, NE = (kSetupTH + 2) * TW, IT = (NE + 255) / 256;
   __shared__ float sT[kSetupTH + 2][kSetupTW + 2];
   __shared__ float sI[kSetupTH + 2][kSetupTW + 2];
   __shared__ float sU[kSetupTH][kSetupTW];
@@ -186,21 +184,58 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   if (c.active && !c.active[pr]) return;
   const int32_t t = blockIdx.x % tiles_per_pair;
   const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
-  const Img i1 = level_img(c, c.pairs[pr].f1, g);
-  const Img i2 = level_img(c, c.pairs[pr].f2, g);
-  const float* cu = g.has_coarse ? uv_buf(c, pr, coarse_code, g.n0) : nullptr;
-  const float* cv = cu ? cu + (int64_t)g.cw * g.ch : nullptr;
-  for (int e = threadIdx.x; e < (kSetupTH + 2) * (kSetupTW + 2); e += 256) {
-    const int ty = e / (kSetupTW + 2), tx = e % (kSetupTW + 2);
+  const PairDesc pd = c.pairs[pr];
+  const uint8_t* y1 = nullptr;
+  const uint8_t* y2 = nullptr;
+  const float* f1 = nullptr;
+  const float* f2 = nullptr;
+  int64_t p1, p2;
+  if constexpr (U8) {
+    const FrameDesc d1 = c.frames[pd.f1], d2 = c.frames[pd.f2];
+    y1 = d1.y;
+    y2 = d2.y;
+    p1 = d1.pitch;
+    p2 = d2.pitch;
+  } else {
+    f1 = c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off;
+    f2 = c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off;
+    p1 = p2 = g.w;
+  }
+  auto at1 = [&](int32_t xx, int32_t yy) -> float {
+    if constexpr (U8) return (float)y1[(int64_t)yy * p1 + xx];
+    else return f1[(int64_t)yy * p1 + xx];
+  };
+  auto at2 = [&](int32_t xx, int32_t yy) -> float {
+    if constexpr (U8) return (float)y2[(int64_t)yy * p2 + xx];
+    else return f2[(int64_t)yy * p2 + xx];
+  };
+  const float* cu = COARSE ? uv_buf(c, pr, coarse_code, g.n0) : nullptr;
+  const float* cv = COARSE ? cu + (int64_t)g.cw * g.ch : nullptr;
+  float rT[IT], rI[IT], rU[IT], rV[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = min((int)threadIdx.x + i * 256, NE - 1);
+    const int ty = e / TW, tx = e % TW;
     const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
     float u0 = 0.f, v0 = 0.f;
-    if (cu) start_flow(cu, cv, g, x, y, &u0, &v0);
-    sT[ty][tx] = warp_sample(i2, g, x, y, u0, v0);
-    sI[ty][tx] = i1.at(x, y);
+    if constexpr (COARSE) start_flow(cu, cv, g, x, y, &u0, &v0);
+    const float fu = floorf(u0), fv = floorf(v0);
+    rT[i] = bilinear_split(at2, g.w, g.h, x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
+    rI[i] = at1(x, y);
+    rU[i] = u0;
+    rV[i] = v0;
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = threadIdx.x + i * 256;
+    if (e >= NE) break;
+    const int ty = e / TW, tx = e % TW;
+    sT[ty][tx] = rT[i];
+    sI[ty][tx] = rI[i];
     const int iy = ty - 1, ix = tx - 1;
     if (iy >= 0 && iy < kSetupTH && ix >= 0 && ix < kSetupTW) {
-      sU[iy][ix] = u0;
-      sV[iy][ix] = v0;
+      sU[iy][ix] = rU[i];
+      sV[iy][ix] = rV[i];
     }
   }
   __syncthreads();
@@ -407,9 +442,11 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
 // halo tile and no barrier: waves are independent, which lets the loads of
 // one wave overlap the arithmetic of another.  Rows above and below the
 // image are mirrored, which reproduces clamp-to-edge bitwise (same argument
-// as for the tile kernel).  ns <= K sweeps run per launch.
+// as for the tile kernel).  Exactly K sweeps run per launch: with a run-time
+// count the window slots become run-time selections (about one extra move
+// per arithmetic instruction), so shorter passes use a smaller K instance.
 // One input step of the streaming kernel: input row ii enters sweep 0 and
-// every sweep s <= ns advances row ii - s.  U = ii mod 3 and the sweep index
+// every sweep s <= K advances row ii - s.  U = ii mod 3 and the sweep index
 // are template parameters so that every window slot is a compile-time
 // register (template recursion instead of a loop the compiler may not unroll).
 template <int K>
@@ -417,7 +454,7 @@ struct StStep {
   float4 (&win)[K][3];
   float2 (&ring)[K + 1][3][64];
   int lane;
-  int32_t ns, y0, y1, w;
+  int32_t y0, y1, w;
   float* du;
   float* dv;
   int32_t cx0, cx1;
@@ -426,7 +463,6 @@ struct StStep {
   template <int U, int S>
   __device__ __forceinline__ void sweep(int32_t ii) {
     if constexpr (S <= K) {
-      if (S > ns) return;
       constexpr int RING = K + 1;
       const float4 A = win[S - 1][(U - S + 2 + 3 * K) % 3];
       const float4 B = win[S - 1][(U - S + 3 * K) % 3];
@@ -446,7 +482,7 @@ struct StStep {
       jac_update(ub0, vb0, ca.x, cb.x, cc.x, &N.x, &N.z);
       jac_update(ub1, vb1, ca.y, cb.y, cc.y, &N.y, &N.w);
       if constexpr (S < K) win[S][(U - S + 3 * K) % 3] = N;
-      if (S == ns) {
+      if constexpr (S == K) {
         const int32_t r = ii - S;
         if (r >= y0 && r < y1) {
           const int64_t o = (int64_t)r * w;
@@ -465,22 +501,26 @@ struct StStep {
     }
   }
 
+  // Input row ii sits in prefetch slot U; once it has entered the window and
+  // the ring, the slot is refilled with row ii + 3 (three rows of loads in
+  // flight per wave).
   template <int U, typename F>
-  __device__ __forceinline__ void step(int32_t ii, float4& nuv, float2& na, float2& nb, float2& nc, F&& load_row) {
+  __device__ __forceinline__ void step(int32_t ii, float4 (&nuv)[3], float2 (&na)[3], float2 (&nb)[3],
+                                       float2 (&nc)[3], F&& load_row) {
     constexpr int RING = K + 1;
-    win[0][U] = nuv;
+    win[0][U] = nuv[U];
     const int rs = ((ii % RING) + RING) % RING;
-    ring[rs][0][lane] = na;
-    ring[rs][1][lane] = nb;
-    ring[rs][2][lane] = nc;
-    load_row(ii + 1);
+    ring[rs][0][lane] = na[U];
+    ring[rs][1][lane] = nb[U];
+    ring[rs][2][lane] = nc[U];
+    load_row(ii + 3, nuv[U], na[U], nb[U], nc[U]);
     sweep<U, 1>(ii);
   }
 };
 
 template <int K>
 __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
-                                                      int32_t ns, int32_t strips, int32_t bands, int32_t band_h) {
+                                                      int32_t strips, int32_t bands, int32_t band_h) {
   constexpr int RING = K + 1;
   __shared__ float2 ring[4][RING][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
   const int lane = threadIdx.x & 63;
@@ -516,19 +556,35 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
 
   int32_t i = y0 - K - 1;
   i -= ((i % 3) + 3) % 3;  // start on a multiple of 3 so that slots are static
-  const int32_t i_end = y1 - 1 + ns;
-  // prefetch of input row i
-  float4 nuv;
-  float2 na, nb, nc;
-  auto load_row = [&](int32_t row) {
+  const int32_t i_end = y1 - 1 + K;
+  // Rows are read as float2 where a lane's two columns are adjacent and the
+  // pair is 8-byte aligned in every row (even width, even first column);
+  // lanes whose columns are mirrored at the image border read scalars.
+  const bool vec = (g.w % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
+                     reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
+                     reinterpret_cast<uintptr_t>(pc)) % 8 == 0);
+  auto load_row = [&](int32_t row, float4& uv, float2& a, float2& b, float2& cc) {
     const int64_t r = (int64_t)reflect(row, g.h) * g.w;
-    nuv = make_float4(su[r + gx0], su[r + gx1], sv[r + gx0], sv[r + gx1]);
-    na = make_float2(pa[r + gx0], pa[r + gx1]);
-    nb = make_float2(pb[r + gx0], pb[r + gx1]);
-    nc = make_float2(pc[r + gx0], pc[r + gx1]);
+    if (vec) {
+      const float2 u2 = *reinterpret_cast<const float2*>(su + r + gx0);
+      const float2 v2 = *reinterpret_cast<const float2*>(sv + r + gx0);
+      uv = make_float4(u2.x, u2.y, v2.x, v2.y);
+      a = *reinterpret_cast<const float2*>(pa + r + gx0);
+      b = *reinterpret_cast<const float2*>(pb + r + gx0);
+      cc = *reinterpret_cast<const float2*>(pc + r + gx0);
+    } else {
+      uv = make_float4(su[r + gx0], su[r + gx1], sv[r + gx0], sv[r + gx1]);
+      a = make_float2(pa[r + gx0], pa[r + gx1]);
+      b = make_float2(pb[r + gx0], pb[r + gx1]);
+      cc = make_float2(pc[r + gx0], pc[r + gx1]);
+    }
   };
-  load_row(i);
-  StStep<K> st{win, ring[wv], lane, ns, y0, y1, g.w, du, dv, cx0, cx1, in0, in1};
+  float4 nuv[3];
+  float2 na[3], nb[3], nc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
+  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, cx0, cx1, in0, in1};
   for (; i <= i_end; i += 3) {
     st.template step<0>(i, nuv, na, nb, nc, load_row);
     st.template step<1>(i + 1, nuv, na, nb, nc, load_row);
@@ -575,7 +631,10 @@ bool variant_fits(int v, int32_t k, const LevelGeom& g) {
 
 scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const LevelGeom& g, int64_t n_pairs,
                          int32_t src, int32_t dst, int32_t ns, hipStream_t s) {
+  static constexpr const char* kLevelTimer[] = {"hs_jacobi_l0", "hs_jacobi_l1", "hs_jacobi_l2", "hs_jacobi_l3",
+                                                "hs_jacobi_l4", "hs_jacobi_l5", "hs_jacobi_l6"};
   KernelTimer timer("hs_jacobi", s);
+  KernelTimer timer_l(kLevelTimer[std::min(g.level, 6)], s);
   if (jc.variant == 0) {
     const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
     for (int32_t it = 0; it < ns; ++it) {
@@ -589,18 +648,29 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
   }
   const JacobiVariant v = kVariants[jc.variant];
   if (v.rows == 0) {
-    const int32_t K = v.waves;
+    // the streaming kernel runs exactly K sweeps (a compile-time count: the
+    // window registers then need no run-time selection); a pass of ns <= the
+    // variant's maximum uses the K = ns instance
+    const int32_t K = ns;
+    if (K < 1 || K > v.waves) { set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL; }
     const int32_t strips = (g.w + (128 - 2 * K) - 1) / (128 - 2 * K);
-    const int32_t bands = (g.h + kBandRows - 1) / kBandRows;
+    // bands: enough independent waves to fill the chip (about 24 per CU), but
+    // no band shorter than 64 rows (each band re-reads a 2K + 1 row halo)
+    const int64_t want = 24 * 256;
+    int64_t bh = (int64_t)g.h * strips * n_pairs / want;
+    bh = std::max<int64_t>(64, std::min<int64_t>(kBandRows, bh));
+    const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
     const int32_t band_h = (g.h + bands - 1) / bands;
     const int64_t units = (int64_t)strips * bands * n_pairs;
     const int64_t grid = (units + 3) / 4;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    const dim3 gd((unsigned)grid), bd(256);
     switch (K) {
-      case 6: hipLaunchKernelGGL((k_hs_jacobi_st<6>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
-      case 8: hipLaunchKernelGGL((k_hs_jacobi_st<8>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
-      case 10: hipLaunchKernelGGL((k_hs_jacobi_st<10>), dim3((unsigned)grid), dim3(256), 0, s, c, g, src, dst, ns, strips, bands, band_h); break;
-      default: set_error("internal: bad streaming Jacobi variant"); return SCN_EINVAL;
+#define SCN_ST(k) \
+  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
+      SCN_ST(1) SCN_ST(2) SCN_ST(3) SCN_ST(4) SCN_ST(5) SCN_ST(6) SCN_ST(7) SCN_ST(8) SCN_ST(9) SCN_ST(10)
+#undef SCN_ST
+      default: set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL;
     }
     SCN_LAUNCHED("jacobi launch");
     return SCN_OK;
@@ -677,8 +747,20 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       const int64_t tpp = (int64_t)tiles_x * tiles_y;
       if (tpp * ch.n_pairs > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
       KernelTimer timer("hs_setup", s);
-      hipLaunchKernelGGL(k_hs_setup, dim3((unsigned)(tpp * ch.n_pairs)), dim3(256), 0, s, c, g, coarse, start_dst,
-                         alpha2, tiles_x, (int32_t)tpp);
+      const dim3 grid((unsigned)(tpp * ch.n_pairs));
+      const bool u8 = g.level == 0, co = g.has_coarse != 0;
+      if (u8 && co)
+        hipLaunchKernelGGL((k_hs_setup<true, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
+                           (int32_t)tpp);
+      else if (u8)
+        hipLaunchKernelGGL((k_hs_setup<true, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
+                           (int32_t)tpp);
+      else if (co)
+        hipLaunchKernelGGL((k_hs_setup<false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
+                           (int32_t)tpp);
+      else
+        hipLaunchKernelGGL((k_hs_setup<false, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
+                           tiles_x, (int32_t)tpp);
     }
     SCN_LAUNCHED("setup launch");
     int32_t cur = start_dst;

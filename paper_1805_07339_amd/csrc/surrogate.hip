@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
     for (int nb = 0; nb < NB; ++nb) {
       const bf16x8 b = ld8(wf + (nb * 16 + r16) * 32 + kg * 8);
 #pragma unroll
-      for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+      for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b, a[mr], acc[mr][nb]);
     }
   } else {
     for (int tap = 0; tap < 9; ++tap) {
@@ -124,26 +124,36 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
         for (int nb = 0; nb < NB; ++nb) {
           const bf16x8 b = ld8(wf + ((int64_t)(tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8));
 #pragma unroll
-          for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
+          for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b, a[mr], acc[mr][nb]);
         }
       }
     }
   }
+  // lane (r16, kg) holds channels nb*16 + 4kg .. +3 of pixel r16 of each block
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr) {
+    const int64_t m = base + mr * 16 + r16;
+    if (m >= M) continue;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + r16;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t m = base + mr * 16 + kg * 4 + i;
-        if (m >= M || co >= CO) continue;
-        float v = acc[mr][nb][i] + bias[co];
-        if (RELU) v = fmaxf(v, 0.f);
-        if constexpr (L == kLayers - 1)
-          reinterpret_cast<float*>(y)[m * CO + co] = v;
-        else
-          reinterpret_cast<bf16_t*>(y)[m * CO + co] = f2bf(v);
+      const int co = nb * 16 + 4 * kg;
+      const float4 bv = *reinterpret_cast<const float4*>(bias + co);
+      float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
+      float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
+      if (RELU) {
+        v0 = fmaxf(v0, 0.f);
+        v1 = fmaxf(v1, 0.f);
+        v2 = fmaxf(v2, 0.f);
+        v3 = fmaxf(v3, 0.f);
+      }
+      if constexpr (L == kLayers - 1) {
+        if (co == 0) *reinterpret_cast<float2*>(reinterpret_cast<float*>(y) + m * CO) = make_float2(v0, v1);
+      } else {
+        static_assert(L == kLayers - 1 || CO % 4 == 0, "epilogue stores 4 channels per lane");
+        uint2 pk;
+        pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+        pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+        *reinterpret_cast<uint2*>(reinterpret_cast<bf16_t*>(y) + m * CO + co) = pk;
       }
     }
   }
@@ -153,22 +163,32 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // output pixels of one image; the (TOH-1)S+3 x (TOW-1)S+3 effective input
 // pixels it reads (zero outside the image, nearest-upsampled for x2 layers)
 // are loaded once with 16-byte loads into LDS (channel stride padded by 8 to
-// spread banks), and all nine taps read their A fragments from there, so each
+// spread banks), and all nine taps read their fragments from there, so each
 // input element crosses the memory hierarchy once per workgroup instead of
 // nine times.  Each wave owns 16 * MR output pixels (MR pixel blocks of 16
 // along a row) x all output channels.
-template <int L, int TOH, int TOW>
-__global__ void __launch_bounds__(256) k_conv_fwd_lds(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
-                                                      void* __restrict__ y, CGeom g, int32_t tiles_x,
-                                                      int32_t tiles_per_img) {
+//
+// Latency: every thread issues all of its tile loads before the first LDS
+// store, and the weight fragments of the next (tap row, channel block) step
+// are requested while the current step's MFMAs run.  The MFMA takes the
+// weights as its first operand, so a lane's accumulator holds four
+// consecutive output channels of one pixel and the epilogue stores 8 bytes
+// per lane.  BLDS stages the whole weight tensor in LDS as well.
+template <int L, int TOH, int TOW, int NWAVE, bool BLDS>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __restrict__ x,
+                                                             const uint8_t* __restrict__ blob, void* __restrict__ y,
+                                                             CGeom g, int32_t tiles_x, int32_t tiles_per_img) {
   constexpr LayerDef D = kNet[L];
-  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16;
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16, NCB = CI / 32;
   constexpr bool UP = D.up != 0, RELU = D.relu != 0;
   constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
-  constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / 4;
-  static_assert(CI % 32 == 0 && TOW % 16 == 0 && NBLK % 4 == 0, "tile shape");
+  constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
+  constexpr int NT = 64 * NWAVE;
+  constexpr int WELEMS = BLDS ? 9 * COP * CI : 8;
+  static_assert(CI % 32 == 0 && TOW % 16 == 0 && NBLK % NWAVE == 0, "tile shape");
+  static_assert(CO % 4 == 0 || L == kLayers - 1, "epilogue stores 4 channels per lane");
   __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
-  const bf16_t* wf = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
+  __shared__ __attribute__((aligned(16))) bf16_t wlds[WELEMS];
   const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
@@ -176,27 +196,110 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const bf16_t* __restrict__
   const int t = blockIdx.x % tiles_per_img;
   const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
   const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
-  for (int e = tid; e < IH * IW * (CI / 8); e += 256) {
+
+  // ---- stage: all global loads first, then all LDS stores
+  constexpr int NW8 = BLDS ? WELEMS / 8 : 0, WIT = (NW8 + NT - 1) / NT;
+  constexpr int NE = IH * IW * (CI / 8), IT = (NE + NT - 1) / NT;
+  const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
+  uint4 wreg[WIT > 0 ? WIT : 1];
+#pragma unroll
+  for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
+  uint4 treg[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = min(tid + i * NT, NE - 1);
     const int ch = e % (CI / 8), p = e / (CI / 8);
-    const int py = p / IW, px = p % IW;
-    const int iy = iy0 + py, ix = ix0 + px;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
-      const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
-      v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
-    }
-    *reinterpret_cast<uint4*>(tile + (py * IW + px) * CP + ch * 8) = v;
+    const int iy = iy0 + p / IW, ix = ix0 + p % IW;
+    const bool ok = iy >= 0 && iy < g.he && ix >= 0 && ix < g.we;
+    const int sy = ok ? (UP ? iy >> 1 : iy) : 0, sx = ok ? (UP ? ix >> 1 : ix) : 0;
+    const uint4 v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
+    treg[i] = ok ? v : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < WIT; ++i)
+    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    if (e < NE) *reinterpret_cast<uint4*>(tile + (e / (CI / 8)) * CP + (e % (CI / 8)) * 8) = treg[i];
   }
   __syncthreads();
+
+  const bf16_t* wf = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
+  auto bfrag = [&](int tap, int nb, int cb) -> bf16x8 {
+    return ld8(wf + (tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8);
+  };
   f32x4 acc[MR][NB];
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
+  if constexpr (S == 1) {
+    // Stride 1: the fragment of tap (ky, kx+1) is the tap (ky, kx) fragment of
+    // the next pixel, i.e. the next lane of the 16-lane row.  Read the kx = 0
+    // fragment once, plus pixels 16 and 17 of the block in lanes 0 and 1, and
+    // rotate within rows (DPP row_ror) for kx = 1, 2.
+    constexpr int NST = 3 * NCB;  // steps: (ky, channel block)
+    bf16x8 bq[2][3][NB];
 #pragma unroll
-    for (int cb = 0; cb < CI / 32; ++cb) {
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) bq[0][kx][nb] = bfrag(kx, nb, 0);
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+      const int ky = st / NCB, cb = st % NCB, cur = st & 1;
+      if (st + 1 < NST) {
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) bq[cur ^ 1][kx][nb] = bfrag(((st + 1) / NCB) * 3 + kx, nb, (st + 1) % NCB);
+      }
+      bf16x8 a0[MR], a1[MR], a2[MR];
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        const int blk = wv * MR + mr;
+        const int orow = blk / BPR, c0 = (blk % BPR) * 16;
+        const bf16_t* rowp = tile + ((orow + ky) * IW) * CP + cb * 32 + kg * 8;
+        const bf16x8 f0 = ld8(rowp + (c0 + r16) * CP);
+        bf16x8 gx = f0;
+        if (r16 < 2) gx = ld8(rowp + (c0 + 16 + r16) * CP);
+        const uint4 u0 = __builtin_bit_cast(uint4, f0), ug = __builtin_bit_cast(uint4, gx);
+        const uint4 t1 = r16 == 0 ? ug : u0;  // lane 0 carries pixel 16
+        const uint4 t2 = r16 < 2 ? ug : u0;   // lanes 0, 1 carry pixels 16, 17
+        uint4 s1, s2;
+        s1.x = __builtin_amdgcn_update_dpp(0u, t1.x, 0x12F, 0xf, 0xf, false);  // row_ror:15
+        s1.y = __builtin_amdgcn_update_dpp(0u, t1.y, 0x12F, 0xf, 0xf, false);
+        s1.z = __builtin_amdgcn_update_dpp(0u, t1.z, 0x12F, 0xf, 0xf, false);
+        s1.w = __builtin_amdgcn_update_dpp(0u, t1.w, 0x12F, 0xf, 0xf, false);
+        s2.x = __builtin_amdgcn_update_dpp(0u, t2.x, 0x12E, 0xf, 0xf, false);  // row_ror:14
+        s2.y = __builtin_amdgcn_update_dpp(0u, t2.y, 0x12E, 0xf, 0xf, false);
+        s2.z = __builtin_amdgcn_update_dpp(0u, t2.z, 0x12E, 0xf, 0xf, false);
+        s2.w = __builtin_amdgcn_update_dpp(0u, t2.w, 0x12E, 0xf, 0xf, false);
+        a0[mr] = f0;
+        a1[mr] = __builtin_bit_cast(bf16x8, s1);
+        a2[mr] = __builtin_bit_cast(bf16x8, s2);
+      }
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int mr = 0; mr < MR; ++mr)
+            acc[mr][nb] = mfma(bq[cur][kx][nb], kx == 0 ? a0[mr] : (kx == 1 ? a1[mr] : a2[mr]), acc[mr][nb]);
+    }
+  } else {
+    constexpr int NST = 9 * NCB;  // steps: (tap, channel block)
+    bf16x8 bq[2][NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) bq[0][nb] = bfrag(0, nb, 0);
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+      const int tap = st / NCB, cb = st % NCB, cur = st & 1;
+      const int ky = tap / 3, kx = tap % 3;
+      if (st + 1 < NST) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bq[cur ^ 1][nb] = bfrag((st + 1) / NCB, nb, (st + 1) % NCB);
+      }
       bf16x8 a[MR];
 #pragma unroll
       for (int mr = 0; mr < MR; ++mr) {
@@ -205,31 +308,38 @@ __global__ void __launch_bounds__(256) k_conv_fwd_lds(const bf16_t* __restrict__
         a[mr] = ld8(tile + ((orow * S + ky) * IW + ocol * S + kx) * CP + cb * 32 + kg * 8);
       }
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const bf16x8 b = ld8(wf + ((int64_t)(tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8));
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(a[mr], b, acc[mr][nb]);
-      }
+        for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(bq[cur][nb], a[mr], acc[mr][nb]);
     }
   }
+  // lane (r16, kg) holds channels nb*16 + 4kg .. +3 of pixel r16 of each block
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr) {
     const int blk = wv * MR + mr;
-    const int oy = oy0 + blk / BPR;
+    const int oy = oy0 + blk / BPR, ox = ox0 + (blk % BPR) * 16 + r16;
+    if (oy >= g.ho || ox >= g.wo) continue;
+    const int64_t m = ((int64_t)n * g.ho + oy) * g.wo + ox;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + r16;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int ox = ox0 + (blk % BPR) * 16 + kg * 4 + i;
-        if (oy >= g.ho || ox >= g.wo || co >= CO) continue;
-        const int64_t m = ((int64_t)n * g.ho + oy) * g.wo + ox;
-        float v = acc[mr][nb][i] + bias[co];
-        if (RELU) v = fmaxf(v, 0.f);
-        if constexpr (L == kLayers - 1)
-          reinterpret_cast<float*>(y)[m * CO + co] = v;
-        else
-          reinterpret_cast<bf16_t*>(y)[m * CO + co] = f2bf(v);
+      const int co = nb * 16 + 4 * kg;
+      const float4 bv = *reinterpret_cast<const float4*>(bias + co);
+      float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
+      float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
+      if (RELU) {
+        v0 = fmaxf(v0, 0.f);
+        v1 = fmaxf(v1, 0.f);
+        v2 = fmaxf(v2, 0.f);
+        v3 = fmaxf(v3, 0.f);
+      }
+      if constexpr (L == kLayers - 1) {
+        static_assert(CO == 2, "last layer writes (u, v)");
+        if (co == 0) *reinterpret_cast<float2*>(reinterpret_cast<float*>(y) + m * CO) = make_float2(v0, v1);
+      } else {
+        uint2 pk;
+        pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+        pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+        *reinterpret_cast<uint2*>(reinterpret_cast<bf16_t*>(y) + m * CO + co) = pk;
       }
     }
   }
@@ -659,44 +769,72 @@ __global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float*
 // ---------------------------------------------------------------------------
 // residual gate: per pair, mean |I2(x + w) - I1(x)| over full-resolution luma
 // (clamped bilinear warp), in two deterministic stages.
-__global__ void k_gate_partial(const FrameDesc* __restrict__ frames, const PairDesc* __restrict__ pairs,
-                               float* __restrict__ part, int32_t W, int32_t H, int32_t blocks_per_pair) {
-  __shared__ float red[256];
+// Full-resolution flow of the network (x2 bilinear of the half-resolution
+// output, written to the pair's output) fused with the gate statistic
+// |I2(x + w) - I1(x)| (clamped bilinear warp of luma), reduced per block.
+__global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half, const FrameDesc* __restrict__ frames,
+                                                 const PairDesc* __restrict__ pairs, float* __restrict__ part,
+                                                 int32_t h, int32_t w, int32_t blocks_per_pair) {
+  // each thread: 8 consecutive pixels of one row (W is a multiple of 8)
+  __shared__ float red[4];
+  const int32_t W = 2 * w, H = 2 * h;
   const int64_t p = blockIdx.x / blocks_per_pair;
-  const int64_t px = (int64_t)(blockIdx.x % blocks_per_pair) * 256 + threadIdx.x;
+  const int32_t q = (blockIdx.x % blocks_per_pair) * 256 + threadIdx.x;  // 8-pixel group
   float r = 0.f;
-  if (px < (int64_t)W * H) {
-    const int32_t x = (int32_t)(px % W), y = (int32_t)(px / W);
+  if (q < (W / 8) * H) {
+    const int32_t y = q / (W / 8), xb = (q % (W / 8)) * 8;
     const PairDesc pd = pairs[p];
     const FrameDesc f1 = frames[pd.f1], f2 = frames[pd.f2];
-    const float u = pd.out[px], v = pd.out[(int64_t)W * H + px];
-    const float fu = floorf(u), fv = floorf(v);
-    int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
-    float fx = u - fu, fy = v - fv;
-    if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
-    if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
-    const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
+    const float* hp = half + p * (int64_t)h * w * 2;
     const uint8_t* a = f2.y;
-    const float top = (1.f - fx) * a[(int64_t)yi * f2.pitch + xi] + fx * a[(int64_t)yi * f2.pitch + x1];
-    const float bot = (1.f - fx) * a[(int64_t)y1 * f2.pitch + xi] + fx * a[(int64_t)y1 * f2.pitch + x1];
-    r = fabsf((1.f - fy) * top + fy * bot - (float)f1.y[(int64_t)y * f1.pitch + x]);
+    const int32_t p2 = (int32_t)f2.pitch;
+    const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
+    float fu8[8], fv8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int32_t x = xb + k;
+      const float2 f = full_flow_at(hp, x, y, h, w);
+      fu8[k] = f.x;
+      fv8[k] = f.y;
+      const float fu = floorf(f.x), fv = floorf(f.y);
+      int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
+      float fx = f.x - fu, fy = f.y - fv;
+      if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
+      if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
+      const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
+      const float top = (1.f - fx) * a[yi * p2 + xi] + fx * a[yi * p2 + x1];
+      const float bot = (1.f - fx) * a[y1 * p2 + xi] + fx * a[y1 * p2 + x1];
+      r += fabsf((1.f - fy) * top + fy * bot - (float)row1[x]);
+    }
+    float* ou = pd.out + (int64_t)y * W + xb;
+    float* ov = ou + (int64_t)W * H;
+    *reinterpret_cast<float4*>(ou) = make_float4(fu8[0], fu8[1], fu8[2], fu8[3]);
+    *reinterpret_cast<float4*>(ou + 4) = make_float4(fu8[4], fu8[5], fu8[6], fu8[7]);
+    *reinterpret_cast<float4*>(ov) = make_float4(fv8[0], fv8[1], fv8[2], fv8[3]);
+    *reinterpret_cast<float4*>(ov + 4) = make_float4(fv8[4], fv8[5], fv8[6], fv8[7]);
   }
-  red[threadIdx.x] = r;
+  // wave reduction, then across the four waves (fixed order: deterministic)
+  for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_gate_final(const float* __restrict__ part, int32_t blocks_per_pair, int64_t n_pairs, float inv_px,
-                             float tau, const PairDesc* __restrict__ pairs, uint8_t* __restrict__ active) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
+// One workgroup per pair: fixed-order strided sums, then a fixed tree, so the
+// statistic is deterministic and the partials are read coalesced.
+__global__ void __launch_bounds__(256) k_gate_final(const float* __restrict__ part, int32_t blocks_per_pair,
+                                                    float inv_px, float tau, const PairDesc* __restrict__ pairs,
+                                                    uint8_t* __restrict__ active) {
+  __shared__ float red[4];
+  const int64_t p = blockIdx.x;
+  const float* src = part + p * blocks_per_pair;
   float s = 0.f;
-  for (int b = 0; b < blocks_per_pair; ++b) s += part[p * blocks_per_pair + b];
-  const float r = s * inv_px;
+  for (int b = threadIdx.x; b < blocks_per_pair; b += 256) s += src[b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const float r = ((red[0] + red[1]) + (red[2] + red[3])) * inv_px;
   const uint8_t a = r > tau ? 1 : 0;
   active[p] = a;
   const PairDesc pd = pairs[p];
@@ -826,24 +964,35 @@ CGeom layer_geom(const NetDims& d, int l, int64_t n) {
 
 constexpr int kMR = 2;  // 16-pixel row blocks per wave
 
-// Output tile (rows x columns) of the LDS-tiled forward kernel per layer.
-template <int L> struct FwdTile { static constexpr int TOH = kNet[L].stride == 2 ? 4 : 8, TOW = 32; };
+// Output tile (rows x columns), waves per workgroup and weights-in-LDS choice
+// of the LDS-tiled forward kernel per layer: conv5 and conv6 (few output
+// channels, small weights) keep the whole weight tensor in LDS next to a
+// 16 x 32 output tile.
+template <int L> struct FwdTile {
+  static constexpr bool BLDS = (L == 4 || L == 5);
+  static constexpr int TOH = kNet[L].stride == 2 ? 4 : (BLDS ? 16 : 8), TOW = 32, NWAVE = BLDS ? 8 : 4;
+};
+
+constexpr const char* kFwdTimer[kLayers] = {"conv_fwd1", "conv_fwd2", "conv_fwd3", "conv_fwd4", "conv_fwd5",
+                                             "conv_fwd6"};
 
 template <int L>
 scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom& g, hipStream_t s) {
   KernelTimer timer("conv_fwd", s);
+  KernelTimer timer_l(kFwdTimer[L], s);
   if constexpr (L == 0) {  // 2 input channels: K = 18 fits one MFMA K block, no tiling needed
     const int64_t M = (int64_t)g.n * g.ho * g.wo;
     const int64_t per_wg = 4 * 16 * kMR;
     const int64_t grid = (M + per_wg - 1) / per_wg;
     hipLaunchKernelGGL((k_conv_fwd<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g);
   } else {
-    constexpr int TOH = FwdTile<L>::TOH, TOW = FwdTile<L>::TOW;
+    constexpr int TOH = FwdTile<L>::TOH, TOW = FwdTile<L>::TOW, NW = FwdTile<L>::NWAVE;
+    constexpr bool BL = FwdTile<L>::BLDS;
     const int32_t tx = (g.wo + TOW - 1) / TOW, ty = (g.ho + TOH - 1) / TOH;
     const int64_t grid = (int64_t)tx * ty * g.n;
     if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
-    hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g, tx,
-                       tx * ty);
+    hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y,
+                       g, tx, tx * ty);
   }
   SCN_LAUNCHED("conv forward launch");
   return SCN_OK;
@@ -941,19 +1090,20 @@ scn_status launch_flow_up(const float* half, const PairDesc* pairs, const NetDim
   return SCN_OK;
 }
 
-scn_status launch_gate(const FrameDesc* frames, const PairDesc* pairs, float* part, int32_t W, int32_t H, int64_t n,
-                       float tau, uint8_t* active, hipStream_t s) {
-  const int32_t bpp = (int32_t)(((int64_t)W * H + 255) / 256);
+scn_status launch_up_gate(const float* half, const FrameDesc* frames, const PairDesc* pairs, float* part,
+                          const NetDims& d, int64_t n, float tau, uint8_t* active, hipStream_t s) {
+  const int32_t W = 2 * d.w, H = 2 * d.h;
+  const int32_t bpp = (int32_t)(((int64_t)(W / 8) * H + 255) / 256);
   KernelTimer timer("gate", s);
-  hipLaunchKernelGGL(k_gate_partial, dim3((unsigned)(bpp * n)), dim3(256), 0, s, frames, pairs, part, W, H, bpp);
-  SCN_LAUNCHED("gate launch");
-  hipLaunchKernelGGL(k_gate_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, bpp, n,
+  hipLaunchKernelGGL(k_up_gate, dim3((unsigned)(bpp * n)), dim3(256), 0, s, half, frames, pairs, part, d.h, d.w, bpp);
+  SCN_LAUNCHED("upsample + gate launch");
+  hipLaunchKernelGGL(k_gate_final, dim3((unsigned)n), dim3(256), 0, s, part, bpp,
                      1.f / ((float)W * H), tau, pairs, active);
   SCN_LAUNCHED("gate reduce launch");
   return SCN_OK;
 }
 
-size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) { return align_up((size_t)n * (((size_t)W * H + 255) / 256) * 4); }
+size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) { return align_up((size_t)n * (((size_t)W * H / 8 + 255) / 256 + 1) * 4); }
 
 }  // namespace sg
 
@@ -1137,8 +1287,7 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
       const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
       if ((st = sg::launch_net_input(frames, pairs, b.x, d, n, s)) != SCN_OK) return st;
       if ((st = sg::net_forward(d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
-      if ((st = sg::launch_flow_up(b.half, pairs, d, n, s)) != SCN_OK) return st;
-      if ((st = sg::launch_gate(frames, pairs, gpart, grp.w, grp.h, n, gate_tau, active, s)) != SCN_OK) return st;
+      if ((st = sg::launch_up_gate(b.half, frames, pairs, gpart, d, n, gate_tau, active, s)) != SCN_OK) return st;
       const int64_t fw = (ch.n_frames + 3) / 4;
       hipLaunchKernelGGL(sg::k_zero_bytes, dim3((unsigned)((fw + 255) / 256)), dim3(256), 0, s, (uint32_t*)factive,
                          fw);

@@ -239,26 +239,22 @@ def eval_grid_batch(tex: Texture, xs: torch.Tensor, ys: torch.Tensor, Ms, cs) ->
     return tex.mean + tex.amp * torch.bmm(left, right)
 
 
-def scene_batch_nv12(scene: "Scene", ts: Sequence[int], device="cpu", seed_salt: int = 0) -> torch.Tensor:
-    """uint8 NV12 frames [B, H*3/2, W] of one layered scene at time steps ts,
-    evaluated for all time steps at once (same model as Scene.nv12; the noise
-    stream differs)."""
-    W, H = scene.width, scene.height
-    dev = torch.device(device)
-    B = len(ts)
+def _layers_batch_nv12(layers, maps, W: int, H: int, dev, gen_seed: int, sigma: float) -> torch.Tensor:
+    """Compose hard-edged layers for a batch of frames: maps[l] lists the (M, c)
+    inverse maps of layer l, one per frame; the first layer is the background."""
+    B = len(maps[0])
     xs = torch.arange(W, dtype=torch.float64, device=dev)
     ys = torch.arange(H, dtype=torch.float64, device=dev)
     cxs = 2.0 * torch.arange(W // 2, dtype=torch.float64, device=dev) + 0.5
     cys = 2.0 * torch.arange(H // 2, dtype=torch.float64, device=dev) + 0.5
     Y = U = V = None
-    for lay in scene.layers:
-        maps = [lay.inverse_map(t) for t in ts]
-        Ms = [m for m, _ in maps]
-        cs = [c for _, c in maps]
+    for lay, lm in zip(layers, maps):
+        Ms = [m for m, _ in lm]
+        cs = [c for _, c in lm]
         ty = eval_grid_batch(lay.tex_y, xs, ys, Ms, cs)
         tu = eval_grid_batch(lay.tex_u, cxs, cys, Ms, cs)
         tv = eval_grid_batch(lay.tex_v, cxs, cys, Ms, cs)
-        if lay.shape == "full":
+        if Y is None:
             Y, U, V = ty, tu, tv
             continue
         M = torch.tensor(Ms, dtype=torch.float64, device=dev)
@@ -274,17 +270,26 @@ def scene_batch_nv12(scene: "Scene", ts: Sequence[int], device="cpu", seed_salt:
         U = torch.where(mc, tu, U)
         V = torch.where(mc, tv, V)
     g = torch.Generator(device=dev)
-    g.manual_seed((scene.seed * 1_000_003 + 104729 * (seed_salt + 1) + int(ts[0])) & 0x7FFFFFFFFFFFFFFF)
-    s = scene.noise_sigma
-    if s > 0:
-        Y = Y + s * torch.randn(Y.shape, generator=g, dtype=torch.float64, device=dev)
-        U = U + s * torch.randn(U.shape, generator=g, dtype=torch.float64, device=dev)
-        V = V + s * torch.randn(V.shape, generator=g, dtype=torch.float64, device=dev)
+    g.manual_seed(gen_seed & 0x7FFFFFFFFFFFFFFF)
+    if sigma > 0:
+        Y = Y + sigma * torch.randn(Y.shape, generator=g, dtype=torch.float64, device=dev)
+        U = U + sigma * torch.randn(U.shape, generator=g, dtype=torch.float64, device=dev)
+        V = V + sigma * torch.randn(V.shape, generator=g, dtype=torch.float64, device=dev)
     q = lambda a: torch.clamp(torch.round(a), 0, 255).to(torch.uint8)
     out = torch.empty(B, H * 3 // 2, W, dtype=torch.uint8, device=dev)
     out[:, :H] = q(Y)
     out[:, H:] = torch.stack([q(U), q(V)], dim=-1).reshape(B, H // 2, W)
     return out
+
+
+def scene_batch_nv12(scene: "Scene", ts: Sequence[int], device="cpu", seed_salt: int = 0) -> torch.Tensor:
+    """uint8 NV12 frames [B, H*3/2, W] of one layered scene at time steps ts,
+    evaluated for all time steps at once (same model as Scene.nv12; the noise
+    stream differs)."""
+    maps = [[lay.inverse_map(t) for t in ts] for lay in scene.layers]
+    seed = scene.seed * 1_000_003 + 104729 * (seed_salt + 1) + int(ts[0])
+    return _layers_batch_nv12(scene.layers, maps, scene.width, scene.height, torch.device(device), seed,
+                              scene.noise_sigma)
 
 
 def translation_scene(seed: int, width: int, height: int, n_frames: int, max_shift: float = 2.0,
@@ -416,6 +421,24 @@ def _rig_frame(rig: "RigScene", cam: int, t: int, device) -> torch.Tensor:
     out[:H] = q(Y)
     out[H:] = torch.stack([q(U), q(V)], dim=-1).reshape(H // 2, W)
     return out
+
+
+def rig_batch_nv12(rig: "RigScene", frames: Sequence[Tuple[int, int]], device="cpu") -> torch.Tensor:
+    """uint8 NV12 frames [B, H*3/2, W] of (camera, time step) pairs, evaluated at
+    once (same geometry as RigScene.nv12; the noise stream differs)."""
+    sc = rig.scene
+    W = sc.width
+    maps = []
+    for (d0, d1, vyc) in rig.disp:
+        lm = []
+        for cam, t in frames:
+            tt = 0.35 * math.sin(2.0 * math.pi * t / 150.0)
+            off, k, vy = cam * d0, cam * (d1 - d0) / W, cam * vyc
+            lm.append((((1.0 / (1.0 + k), 0.0), (0.0, 1.0)), (-(off + tt) / (1.0 + k), -vy)))
+        maps.append(lm)
+    cam0, t0 = frames[0]
+    seed = sc.seed * 1_000_003 + 7919 * (t0 * 64 + cam0) + 31
+    return _layers_batch_nv12(sc.layers, maps, W, sc.height, torch.device(device), seed, sc.noise_sigma)
 
 
 # --------------------------------------------------------------------------
