@@ -294,23 +294,42 @@ def c5_workload(scn, torch, dev, args):
                          "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None}}
 
 
-def summarize_rocprof(directory: str) -> str:
+def summarize_rocprof(directory: str, bench_json: str = None) -> str:
     """Short text summary of rocprofv3 CSV output (kernel stats of this library's
-    kernels, and per-kernel sums of any collected counters)."""
+    kernels, and per-kernel sums of any collected counters).  With the bench
+    JSON of the profiled run, also the average duration of the Jacobi launches
+    of its timed region (the last `roofline.launches` Jacobi dispatches)."""
     import csv
     import glob
     out = []
+    if bench_json:
+        info = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        n = int(info["roofline"]["launches"])
+        for f in sorted(glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)):
+            d = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                 for r in csv.DictReader(open(f)) if "k_hs_jacobi" in r["Kernel_Name"]]
+            d = [x for _, x in sorted(d)][-n:]
+            out.append("# timed region of the profiled run: %d Jacobi launches, average %.1f ns "
+                       "(bench.py's own HIP-event average in the same run: %.1f ns)"
+                       % (len(d), sum(d) / max(len(d), 1), info["roofline"]["avg_launch_ms"] * 1e6))
     def short(n):
         n = n.replace("(anonymous namespace)::", "").replace("void ", "")
         return n.split("(")[0]
     for f in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
         out.append("# kernel stats: %s" % os.path.relpath(f, directory))
         out.append("%-48s %8s %14s %12s %7s" % ("kernel", "calls", "total_ns", "avg_ns", "pct"))
+        jac_calls, jac_ns = 0, 0.0
         for r in csv.DictReader(open(f)):
             if "scn::" not in r["Name"] and "copy" not in r["Name"].lower():
                 continue
+            if "k_hs_jacobi" in r["Name"]:
+                jac_calls += int(r["Calls"])
+                jac_ns += float(r["TotalDurationNs"])
             out.append("%-48s %8s %14.0f %12.1f %7.2f" % (short(r["Name"])[:48], r["Calls"], float(r["TotalDurationNs"]),
                                                           float(r["AverageNs"]), float(r["Percentage"])))
+        if jac_calls:
+            out.append("%-48s %8d %14.0f %12.1f" % ("all Jacobi kernels (k_hs_jacobi*)", jac_calls, jac_ns,
+                                                    jac_ns / jac_calls))
     for f in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
         agg = {}
         for r in csv.DictReader(open(f)):
@@ -415,7 +434,7 @@ def read_traffic():
 
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
-        print(summarize_rocprof(sys.argv[2]))
+        print(summarize_rocprof(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else None))
         return
     if len(sys.argv) > 4 and sys.argv[1] == "--traffic-summary":
         print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
