@@ -121,9 +121,10 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     dt = time.perf_counter() - t0
     conv_ms, conv_n = scn.timing_read("conv_fwd")
     per_layer = {}
-    for li in range(1, 7):
-        ms, _ = scn.timing_read("conv_fwd%d" % li)
-        per_layer["conv%d" % li] = ms / args.steps
+    for li in (1, 2, 12, 3, 4, 5, 6):
+        ms, n_l = scn.timing_read("conv_fwd%d" % li)
+        if n_l:
+            per_layer["conv%d" % li if li != 12 else "conv1+2 (fused)"] = ms / args.steps
     gate_ms, _ = scn.timing_read("gate")
     up_ms, _ = scn.timing_read("flow_up")
     fb_ms = {k: scn.timing_read(k)[0] / args.steps for k in ["pyr_down", "hs_setup", "hs_jacobi"]}

@@ -28,6 +28,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -60,13 +61,33 @@ struct ChunkPtrs {
   const uint8_t* factive;  // per frame: some active pair uses it (NULL: all frames)
 };
 
+// Every buffer the kernels touch is device global memory.  Pointers read
+// from the descriptor tables would otherwise be generic (flat) pointers,
+// whose accesses also count against the LDS wait counter and need 64-bit
+// per-lane address arithmetic; passing them through the global address
+// space lets the compiler emit global accesses.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)p;
+}
+// Load of a global element at a (wave-uniform) base plus a 32-bit byte
+// offset: a scalar base and one VGPR offset, no per-lane 64-bit arithmetic.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t byte_off) {
+  return *(const __attribute__((address_space(1))) T*)(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, uint32_t byte_off, T v) {
+  *(__attribute__((address_space(1))) T*)(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // (u, v) buffer codes: 0 and 1 are the pair's ping-pong buffers, 2 is the output.
 __device__ __forceinline__ float* uv_buf(const ChunkPtrs& c, int64_t pair, int code, int64_t n0) {
-  if (code == 2) return c.pairs[pair].out;
-  return c.scratch + pair * c.pair_floats + (int64_t)(kPlaneU0 + 2 * code) * n0;
+  if (code == 2) return as_global(c.pairs[pair].out);
+  return as_global(c.scratch + pair * c.pair_floats + (int64_t)(kPlaneU0 + 2 * code) * n0);
 }
 __device__ __forceinline__ float* plane(const ChunkPtrs& c, int64_t pair, int k, int64_t n0) {
-  return c.scratch + pair * c.pair_floats + (int64_t)k * n0;
+  return as_global(c.scratch + pair * c.pair_floats + (int64_t)k * n0);
 }
 
 // Image of level l of frame slot f: u8 luma at level 0, float pyramid above.
@@ -81,12 +102,12 @@ struct Img {
 __device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const LevelGeom& g) {
   Img im;
   if (g.level == 0) {
-    im.y8 = c.frames[f].y;
+    im.y8 = as_global(c.frames[f].y);
     im.f = nullptr;
     im.pitch = c.frames[f].pitch;
   } else {
     im.y8 = nullptr;
-    im.f = c.pyr + (int64_t)f * c.pyr_floats + g.lvl_off;
+    im.f = as_global(c.pyr + (int64_t)f * c.pyr_floats + g.lvl_off);
     im.pitch = g.w;
   }
   return im;
@@ -118,48 +139,86 @@ __device__ __forceinline__ void start_flow(const float* cu, const float* cv, con
   if (!g.has_coarse) { *u0 = 0.f; *v0 = 0.f; return; }
   const int32_t xi = x >> 1, yi = y >> 1;
   const float xf = (x & 1) ? 0.5f : 0.f, yf = (y & 1) ? 0.5f : 0.f;
-  const int32_t cw = g.cw;
-  auto atu = [&](int32_t xx, int32_t yy) { return cu[(int64_t)yy * cw + xx]; };
-  auto atv = [&](int32_t xx, int32_t yy) { return cv[(int64_t)yy * cw + xx]; };
+  const uint32_t cw4 = 4u * (uint32_t)g.cw;
+  auto atu = [&](int32_t xx, int32_t yy) { return ldg(cu, (uint32_t)yy * cw4 + 4u * (uint32_t)xx); };
+  auto atv = [&](int32_t xx, int32_t yy) { return ldg(cv, (uint32_t)yy * cw4 + 4u * (uint32_t)xx); };
   *u0 = 2.f * bilinear_split(atu, g.cw, g.ch, xi, xf, yi, yf);
   *v0 = 2.f * bilinear_split(atv, g.cw, g.ch, xi, xf, yi, yf);
 }
 
 // ---------------------------------------------------------------------------
 // pyramid: level l = even samples of blur5(level l-1), [1,4,6,4,1]/16
-// horizontal then vertical, clamp-to-edge.  One thread per output pixel.
-__global__ void __launch_bounds__(kThreads) k_pyr_down(ChunkPtrs c, LevelGeom src, LevelGeom dst, int32_t bpf) {
-  const int64_t f = blockIdx.x / bpf;
-  const int64_t p = (int64_t)(blockIdx.x % bpf) * kThreads + threadIdx.x;
-  if (p >= (int64_t)dst.w * dst.h) return;
+// horizontal then vertical, clamp-to-edge.  A workgroup owns 16 x 64 output
+// pixels: it stages the 35 x 131 clamped input pixels in LDS with coalesced
+// loads, forms the horizontal sums of the 35 rows at the 64 even columns, and
+// then the vertical sums, in the same order of operations per pixel as the
+// plain definition (integer sums at level 0, so those are exact).
+constexpr int kPyrTW = 64, kPyrTH = 16, kPyrIW = 2 * kPyrTW + 3, kPyrIH = 2 * kPyrTH + 3;
+template <bool U8>
+__global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, LevelGeom dst, int32_t tiles_x,
+                                                  int32_t tiles_per_frame) {
+  using T = typename std::conditional<U8, int, float>::type;
+  __shared__ T sIn[kPyrIH][kPyrIW + 1];
+  __shared__ T sH[kPyrIH][kPyrTW];
+  const int64_t f = blockIdx.x / tiles_per_frame;
   if (c.factive && !c.factive[f]) return;
-  const int32_t x = (int32_t)(p % dst.w), y = (int32_t)(p / dst.w);
+  const int32_t t = blockIdx.x % tiles_per_frame;
+  const int32_t ox = (t % tiles_x) * kPyrTW, oy = (t / tiles_x) * kPyrTH;
+  const int32_t ix0 = 2 * ox - 2, iy0 = 2 * oy - 2;
   const Img im = level_img(c, (int32_t)f, src);
-  const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
-  float acc = 0.f;
-  if (src.level == 0) {  // exact integer sums of u8 luma
-    const int ki[5] = {1, 4, 6, 4, 1};
-    int s = 0;
+  constexpr int NIN = kPyrIH * kPyrIW, IT = (NIN + 255) / 256;
+  T v[IT];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int32_t yy = clampi(2 * y + j - 2, 0, src.h - 1);
+  for (int i = 0; i < IT; ++i) {
+    const int e = min((int)threadIdx.x + i * 256, NIN - 1);
+    const int32_t yy = clampi(iy0 + e / kPyrIW, 0, src.h - 1), xx = clampi(ix0 + e % kPyrIW, 0, src.w - 1);
+    const uint32_t off = (uint32_t)yy * (uint32_t)im.pitch + (uint32_t)xx;
+    if constexpr (U8) v[i] = (int)ldg(im.y8, off);
+    else v[i] = ldg(im.f, 4u * off);
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = threadIdx.x + i * 256;
+    if (e < NIN) sIn[e / kPyrIW][e % kPyrIW] = v[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPyrIH * kPyrTW; e += 256) {
+    const int r = e / kPyrTW, x = e % kPyrTW;
+    if constexpr (U8) {
+      const int ki[5] = {1, 4, 6, 4, 1};
       int hs = 0;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) hs += ki[i] * (int)im.y8[(int64_t)yy * im.pitch + clampi(2 * x + i - 2, 0, src.w - 1)];
-      s += ki[j] * hs;
-    }
-    acc = (float)s * (1.f / 256.f);
-  } else {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int32_t yy = clampi(2 * y + j - 2, 0, src.h - 1);
+      for (int i = 0; i < 5; ++i) hs += ki[i] * sIn[r][2 * x + i];
+      sH[r][x] = hs;
+    } else {
+      const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
       float hs = 0.f;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) hs += k[i] * im.f[(int64_t)yy * im.pitch + clampi(2 * x + i - 2, 0, src.w - 1)];
-      acc += k[j] * hs;
+      for (int i = 0; i < 5; ++i) hs += k[i] * sIn[r][2 * x + i];
+      sH[r][x] = hs;
     }
   }
-  c.pyr[f * c.pyr_floats + dst.lvl_off + p] = acc;
+  __syncthreads();
+  float* out = c.pyr + f * c.pyr_floats + dst.lvl_off;
+  for (int e = threadIdx.x; e < kPyrTH * kPyrTW; e += 256) {
+    const int ly = e / kPyrTW, x = e % kPyrTW;
+    const int32_t gx = ox + x, gy = oy + ly;
+    if (gx >= dst.w || gy >= dst.h) continue;
+    float acc;
+    if constexpr (U8) {
+      const int ki[5] = {1, 4, 6, 4, 1};
+      int s = 0;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) s += ki[j] * sH[2 * ly + j][x];
+      acc = (float)s * (1.f / 256.f);
+    } else {
+      const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+      acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) acc += k[j] * sH[2 * ly + j][x];
+    }
+    stg(out, 4u * ((uint32_t)gy * (uint32_t)dst.w + (uint32_t)gx), acc);
+  }
 }
 
 // setup = warp + coef fused on 64 x 16 output tiles: the warped image T, the
@@ -192,22 +251,24 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   int64_t p1, p2;
   if constexpr (U8) {
     const FrameDesc d1 = c.frames[pd.f1], d2 = c.frames[pd.f2];
-    y1 = d1.y;
-    y2 = d2.y;
+    y1 = as_global(d1.y);
+    y2 = as_global(d2.y);
     p1 = d1.pitch;
     p2 = d2.pitch;
   } else {
-    f1 = c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off;
-    f2 = c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off;
+    f1 = as_global(c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off);
+    f2 = as_global(c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off);
     p1 = p2 = g.w;
   }
+  // 32-bit byte offsets (a frame or pyramid level is far below 4 GiB)
+  const uint32_t q1 = (uint32_t)p1, q2 = (uint32_t)p2;
   auto at1 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)y1[(int64_t)yy * p1 + xx];
-    else return f1[(int64_t)yy * p1 + xx];
+    if constexpr (U8) return (float)ldg(y1, (uint32_t)yy * q1 + (uint32_t)xx);
+    else return ldg(f1, 4u * ((uint32_t)yy * q1 + (uint32_t)xx));
   };
   auto at2 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)y2[(int64_t)yy * p2 + xx];
-    else return f2[(int64_t)yy * p2 + xx];
+    if constexpr (U8) return (float)ldg(y2, (uint32_t)yy * q2 + (uint32_t)xx);
+    else return ldg(f2, 4u * ((uint32_t)yy * q2 + (uint32_t)xx));
   };
   const float* cu = COARSE ? uv_buf(c, pr, coarse_code, g.n0) : nullptr;
   const float* cv = COARSE ? cu + (int64_t)g.cw * g.ch : nullptr;
@@ -263,13 +324,13 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const float It = sT[hy][hx] - sI[hy][hx];
     const float Itp = It - Ix * u0 - Iy * v0;
     const float den = alpha2 + Ix * Ix + Iy * Iy;
-    const float r = 1.0f / sqrtf(den);
-    const int64_t p = (int64_t)y * g.w + x;
-    pa[p] = Ix * r;
-    pb[p] = Iy * r;
-    pc[p] = Itp * r;
-    dst[p] = u0;
-    dst[n + p] = v0;
+    const float r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
+    const uint32_t p4 = 4u * ((uint32_t)y * (uint32_t)g.w + (uint32_t)x);
+    stg(pa, p4, Ix * r);
+    stg(pb, p4, Iy * r);
+    stg(pc, p4, Itp * r);
+    stg(dst, p4, u0);
+    stg(dst, p4 + 4u * (uint32_t)n, v0);
   }
 }
 
@@ -449,6 +510,19 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
 // every sweep s <= K advances row ii - s.  U = ii mod 3 and the sweep index
 // are template parameters so that every window slot is a compile-time
 // register (template recursion instead of a loop the compiler may not unroll).
+// Per-lane element at a wave-uniform base: the address is base + a 32-bit
+// lane offset.  The pointers are global-memory pointers (address space 1):
+// generic (flat) accesses would also count against the LDS wait counter, so
+// every wait for the LDS ring would also wait for the rows in flight.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const float gcfloat;
+__device__ __forceinline__ gcfloat& at_off(const float* base, uint32_t byte_off) {
+  return *(gcfloat*)(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ gfloat& at_off(float* base, uint32_t byte_off) {
+  return *(gfloat*)(reinterpret_cast<char*>(base) + byte_off);
+}
+
 template <int K>
 struct StStep {
   float4 (&win)[K][3];
@@ -457,7 +531,7 @@ struct StStep {
   int32_t y0, y1, w;
   float* du;
   float* dv;
-  int32_t cx0, cx1;
+  uint32_t bo0, bo1;  // byte offsets of the lane's two output columns
   bool in0, in1;
 
   template <int U, int S>
@@ -485,14 +559,15 @@ struct StStep {
       if constexpr (S == K) {
         const int32_t r = ii - S;
         if (r >= y0 && r < y1) {
-          const int64_t o = (int64_t)r * w;
+          float* ru = du + (int64_t)r * w;
+          float* rv = dv + (int64_t)r * w;
           if (in0) {
-            du[o + cx0] = N.x;
-            dv[o + cx0] = N.z;
+            at_off(ru, bo0) = N.x;
+            at_off(rv, bo0) = N.z;
           }
           if (in1) {
-            du[o + cx1] = N.y;
-            dv[o + cx1] = N.w;
+            at_off(ru, bo1) = N.y;
+            at_off(rv, bo1) = N.w;
           }
         }
         return;
@@ -524,7 +599,9 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   constexpr int RING = K + 1;
   __shared__ float2 ring[4][RING][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  // wave-uniform from here on: the pair, band, strip, row counters and plane
+  // pointers live in SGPRs and their arithmetic runs on the scalar unit
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t unit = (int64_t)blockIdx.x * 4 + wv;          // (pair, band, strip)
   const int64_t per_pair = (int64_t)strips * bands;
   const int64_t pr = unit / per_pair;
@@ -560,31 +637,41 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   // Rows are read as float2 where a lane's two columns are adjacent and the
   // pair is 8-byte aligned in every row (even width, even first column);
   // lanes whose columns are mirrored at the image border read scalars.
-  const bool vec = (g.w % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
-                   ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
-                     reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
-                     reinterpret_cast<uintptr_t>(pc)) % 8 == 0);
+  // The float2 path is taken by whole waves (interior strips); a wave with
+  // a mirrored border column reads scalars.
+  const bool lane_vec = (g.w % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
+                        ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
+                          reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
+                          reinterpret_cast<uintptr_t>(pc)) % 8 == 0);
+  const bool vec = __all(lane_vec);
+  const uint32_t bo0 = 4u * (uint32_t)gx0, bo1 = 4u * (uint32_t)gx1;
   auto load_row = [&](int32_t row, float4& uv, float2& a, float2& b, float2& cc) {
     const int64_t r = (int64_t)reflect(row, g.h) * g.w;
+    const float *ru = su + r, *rv = sv + r, *ra = pa + r, *rb = pb + r, *rc = pc + r;
     if (vec) {
-      const float2 u2 = *reinterpret_cast<const float2*>(su + r + gx0);
-      const float2 v2 = *reinterpret_cast<const float2*>(sv + r + gx0);
+      typedef float nf2 __attribute__((ext_vector_type(2)));
+      typedef __attribute__((address_space(1))) const nf2 gcnf2;
+      const nf2 u2 = *(gcnf2*)&at_off(ru, bo0);
+      const nf2 v2 = *(gcnf2*)&at_off(rv, bo0);
+      const nf2 a2 = *(gcnf2*)&at_off(ra, bo0);
+      const nf2 b2 = *(gcnf2*)&at_off(rb, bo0);
+      const nf2 c2 = *(gcnf2*)&at_off(rc, bo0);
       uv = make_float4(u2.x, u2.y, v2.x, v2.y);
-      a = *reinterpret_cast<const float2*>(pa + r + gx0);
-      b = *reinterpret_cast<const float2*>(pb + r + gx0);
-      cc = *reinterpret_cast<const float2*>(pc + r + gx0);
+      a = make_float2(a2.x, a2.y);
+      b = make_float2(b2.x, b2.y);
+      cc = make_float2(c2.x, c2.y);
     } else {
-      uv = make_float4(su[r + gx0], su[r + gx1], sv[r + gx0], sv[r + gx1]);
-      a = make_float2(pa[r + gx0], pa[r + gx1]);
-      b = make_float2(pb[r + gx0], pb[r + gx1]);
-      cc = make_float2(pc[r + gx0], pc[r + gx1]);
+      uv = make_float4(at_off(ru, bo0), at_off(ru, bo1), at_off(rv, bo0), at_off(rv, bo1));
+      a = make_float2(at_off(ra, bo0), at_off(ra, bo1));
+      b = make_float2(at_off(rb, bo0), at_off(rb, bo1));
+      cc = make_float2(at_off(rc, bo0), at_off(rc, bo1));
     }
   };
   float4 nuv[3];
   float2 na[3], nb[3], nc[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
-  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, cx0, cx1, in0, in1};
+  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1};
   for (; i <= i_end; i += 3) {
     st.template step<0>(i, nuv, na, nb, nc, load_row);
     st.template step<1>(i + 1, nuv, na, nb, nc, load_row);
@@ -657,7 +744,12 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     // bands: enough independent waves to fill the chip (about 24 per CU), but
     // no band shorter than 64 rows (each band re-reads a 2K + 1 row halo)
     const int64_t want = 24 * 256;
-    int64_t bh = (int64_t)g.h * strips * n_pairs / want;
+    // With an active mask (the surrogate's fallback) only the failing pairs
+    // run and their count is known on the device only; size the bands for
+    // about one pair in eight, so that a small fallback set still fills the
+    // chip (more bands only add waves when more pairs fall back).
+    const int64_t n_eff = c.active ? std::max<int64_t>(1, (n_pairs + 7) / 8) : n_pairs;
+    int64_t bh = (int64_t)g.h * strips * n_eff / want;
     bh = std::max<int64_t>(64, std::min<int64_t>(kBandRows, bh));
     const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
     const int32_t band_h = (g.h + bands - 1) / bands;
@@ -726,11 +818,15 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
   // pyramids of every frame slot of the chunk
   for (int32_t l = 1; l < L; ++l) {
     const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
-    const int64_t bpf = ((int64_t)dg.w * dg.h + kThreads - 1) / kThreads;
-    const int64_t grid = bpf * ch.n_frames;
+    const int32_t tiles_x = (dg.w + kPyrTW - 1) / kPyrTW, tiles_y = (dg.h + kPyrTH - 1) / kPyrTH;
+    const int64_t tpf = (int64_t)tiles_x * tiles_y;
+    const int64_t grid = tpf * ch.n_frames;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     KernelTimer timer("pyr_down", s);
-    hipLaunchKernelGGL(k_pyr_down, dim3((unsigned)grid), dim3(kThreads), 0, s, c, sg, dg, (int32_t)bpf);
+    if (l == 1)
+      hipLaunchKernelGGL(k_pyr_down<true>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
+    else
+      hipLaunchKernelGGL(k_pyr_down<false>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
     SCN_LAUNCHED("pyramid launch");
   }
   int32_t result = -1;  // buffer code holding the coarser level's flow
@@ -750,14 +846,14 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       const dim3 grid((unsigned)(tpp * ch.n_pairs));
       const bool u8 = g.level == 0, co = g.has_coarse != 0;
       if (u8 && co)
-        hipLaunchKernelGGL((k_hs_setup<true, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
-                           (int32_t)tpp);
+        hipLaunchKernelGGL((k_hs_setup<true, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
+                           tiles_x, (int32_t)tpp);
       else if (u8)
-        hipLaunchKernelGGL((k_hs_setup<true, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
-                           (int32_t)tpp);
+        hipLaunchKernelGGL((k_hs_setup<true, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
+                           tiles_x, (int32_t)tpp);
       else if (co)
-        hipLaunchKernelGGL((k_hs_setup<false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x,
-                           (int32_t)tpp);
+        hipLaunchKernelGGL((k_hs_setup<false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
+                           tiles_x, (int32_t)tpp);
       else
         hipLaunchKernelGGL((k_hs_setup<false, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
                            tiles_x, (int32_t)tpp);

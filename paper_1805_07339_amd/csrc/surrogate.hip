@@ -174,58 +174,23 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // weights as its first operand, so a lane's accumulator holds four
 // consecutive output channels of one pixel and the epilogue stores 8 bytes
 // per lane.  BLDS stages the whole weight tensor in LDS as well.
-template <int L, int TOH, int TOW, int NWAVE, bool BLDS>
-__global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __restrict__ x,
-                                                             const uint8_t* __restrict__ blob, void* __restrict__ y,
-                                                             CGeom g, int32_t tiles_x, int32_t tiles_per_img) {
+// MFMA part of the LDS-tiled forward convolution, shared by the kernels that
+// stage a tile: `tile` holds the layer's input tile (SH x SW stored pixels,
+// channel stride CI + 8), `wf` the forward weights [tap][co][ci] (LDS or
+// global).  Each wave owns 16 * MR output pixels (MR pixel blocks of 16 along
+// a row) x all output channels; the epilogue adds the bias, applies ReLU and
+// stores 4 consecutive channels per lane.
+template <int L, int TOH, int TOW, int NWAVE, int SH, int SW>
+__device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, const bf16_t* __restrict__ wf,
+                                              const float* __restrict__ bias, void* __restrict__ y, const CGeom& g,
+                                              int n, int oy0, int ox0) {
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16, NCB = CI / 32;
   constexpr bool UP = D.up != 0, RELU = D.relu != 0;
-  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int CP = CI + 8;
   constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
-  constexpr int NT = 64 * NWAVE;
-  constexpr int WELEMS = BLDS ? 9 * COP * CI : 8;
-  static_assert(CI % 32 == 0 && TOW % 16 == 0 && NBLK % NWAVE == 0, "tile shape");
-  static_assert(CO % 4 == 0 || L == kLayers - 1, "epilogue stores 4 channels per lane");
-  __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
-  __shared__ __attribute__((aligned(16))) bf16_t wlds[WELEMS];
-  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const int n = blockIdx.x / tiles_per_img;
-  const int t = blockIdx.x % tiles_per_img;
-  const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
-  const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
-
-  // ---- stage: all global loads first, then all LDS stores
-  constexpr int NW8 = BLDS ? WELEMS / 8 : 0, WIT = (NW8 + NT - 1) / NT;
-  constexpr int NE = IH * IW * (CI / 8), IT = (NE + NT - 1) / NT;
-  const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
-  uint4 wreg[WIT > 0 ? WIT : 1];
-#pragma unroll
-  for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
-  uint4 treg[IT];
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = min(tid + i * NT, NE - 1);
-    const int ch = e % (CI / 8), p = e / (CI / 8);
-    const int iy = iy0 + p / IW, ix = ix0 + p % IW;
-    const bool ok = iy >= 0 && iy < g.he && ix >= 0 && ix < g.we;
-    const int sy = ok ? (UP ? iy >> 1 : iy) : 0, sx = ok ? (UP ? ix >> 1 : ix) : 0;
-    const uint4 v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
-    treg[i] = ok ? v : make_uint4(0, 0, 0, 0);
-  }
-#pragma unroll
-  for (int i = 0; i < WIT; ++i)
-    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = tid + i * NT;
-    if (e < NE) *reinterpret_cast<uint4*>(tile + (e / (CI / 8)) * CP + (e % (CI / 8)) * 8) = treg[i];
-  }
-  __syncthreads();
-
-  const bf16_t* wf = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
   auto bfrag = [&](int tap, int nb, int cb) -> bf16x8 {
     return ld8(wf + (tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8);
   };
@@ -259,10 +224,11 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
       for (int mr = 0; mr < MR; ++mr) {
         const int blk = wv * MR + mr;
         const int orow = blk / BPR, c0 = (blk % BPR) * 16;
-        const bf16_t* rowp = tile + ((orow + ky) * IW) * CP + cb * 32 + kg * 8;
-        const bf16x8 f0 = ld8(rowp + (c0 + r16) * CP);
+        auto ti = [](int e) { return UP ? (e + 1) >> 1 : e; };  // effective -> stored tile index
+        const bf16_t* rowp = tile + (ti(orow + ky) * SW) * CP + cb * 32 + kg * 8;
+        const bf16x8 f0 = ld8(rowp + ti(c0 + r16) * CP);
         bf16x8 gx = f0;
-        if (r16 < 2) gx = ld8(rowp + (c0 + 16 + r16) * CP);
+        if (r16 < 2) gx = ld8(rowp + ti(c0 + 16 + r16) * CP);
         const uint4 u0 = __builtin_bit_cast(uint4, f0), ug = __builtin_bit_cast(uint4, gx);
         const uint4 t1 = r16 == 0 ? ug : u0;  // lane 0 carries pixel 16
         const uint4 t2 = r16 < 2 ? ug : u0;   // lanes 0, 1 carry pixels 16, 17
@@ -305,7 +271,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
       for (int mr = 0; mr < MR; ++mr) {
         const int blk = wv * MR + mr;
         const int orow = blk / BPR, ocol = (blk % BPR) * 16 + r16;
-        a[mr] = ld8(tile + ((orow * S + ky) * IW + ocol * S + kx) * CP + cb * 32 + kg * 8);
+        a[mr] = ld8(tile + ((orow * S + ky) * SW + ocol * S + kx) * CP + cb * 32 + kg * 8);
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -343,6 +309,152 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
       }
     }
   }
+}
+
+
+template <int L, int TOH, int TOW, int NWAVE, bool BLDS>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __restrict__ x,
+                                                             const uint8_t* __restrict__ blob, void* __restrict__ y,
+                                                             CGeom g, int32_t tiles_x, int32_t tiles_per_img) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16, NCB = CI / 32;
+  constexpr bool UP = D.up != 0, RELU = D.relu != 0;
+  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
+  constexpr int NT = 64 * NWAVE;
+  constexpr int WELEMS = BLDS ? 9 * COP * CI : 8;
+  static_assert(CI % 32 == 0 && TOW % 16 == 0 && NBLK % NWAVE == 0, "tile shape");
+  static_assert(CO % 4 == 0 || L == kLayers - 1, "epilogue stores 4 channels per lane");
+  // x2-upsampled layers keep the source-resolution tile: effective tile
+  // index e (rows or columns) maps to source index (e + 1) / 2 because the
+  // tile origin oy0 - 1, ox0 - 1 is odd (TOH, TOW even), so the tile is a
+  // quarter of the effective one.
+  static_assert(!UP || (S == 1 && TOH % 2 == 0 && TOW % 2 == 0), "upsampled tile shape");
+  constexpr int SH = UP ? IH / 2 + 1 : IH, SW = UP ? IW / 2 + 1 : IW;
+  __shared__ __attribute__((aligned(16))) bf16_t tile[SH * SW * CP];
+  __shared__ __attribute__((aligned(16))) bf16_t wlds[WELEMS];
+  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int n = blockIdx.x / tiles_per_img;
+  const int t = blockIdx.x % tiles_per_img;
+  const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
+  const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
+
+  // ---- stage: all global loads first, then all LDS stores
+  constexpr int NW8 = BLDS ? WELEMS / 8 : 0, WIT = (NW8 + NT - 1) / NT;
+  constexpr int NE = SH * SW * (CI / 8), IT = (NE + NT - 1) / NT;
+  const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
+  uint4 wreg[WIT > 0 ? WIT : 1];
+#pragma unroll
+  for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
+  uint4 treg[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = min(tid + i * NT, NE - 1);
+    const int ch = e % (CI / 8), p = e / (CI / 8);
+    // stored coordinates (source resolution for upsampled layers)
+    const int yy = (UP ? (iy0 >> 1) : iy0) + p / SW, xx = (UP ? (ix0 >> 1) : ix0) + p % SW;
+    const bool ok = yy >= 0 && yy < g.hi && xx >= 0 && xx < g.wi;
+    const int sy = ok ? yy : 0, sx = ok ? xx : 0;
+    const uint4 v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
+    treg[i] = ok ? v : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < WIT; ++i)
+    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT;
+    if (e < NE) *reinterpret_cast<uint4*>(tile + (e / (CI / 8)) * CP + (e % (CI / 8)) * 8) = treg[i];
+  }
+  __syncthreads();
+
+  const bf16_t* wf = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
+  conv_tile_mma<L, TOH, TOW, NWAVE, SH, SW>(tile, wf, bias, y, g, n, oy0, ox0);
+}
+
+// Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
+// kernel.  A workgroup owns TOH x TOW conv2 outputs; it stages the net-input
+// tile (2 channels, zero outside the image), computes the conv1 outputs that
+// conv2's input tile needs straight into LDS (zero outside the image, which
+// is conv2's padding), and runs conv2 from there.  conv1's activation never
+// reaches HBM (the unfused pair writes and re-reads it: 64 B per half-res
+// pixel).  conv1 uses the same fragments, MFMA and rounding as k_conv_fwd<0>,
+// so the conv2 input is bitwise the same.
+template <int TOH, int TOW, int NWAVE>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
+                                                       bf16_t* __restrict__ y, CGeom g1, CGeom g2, int32_t tiles_x,
+                                                       int32_t tiles_per_img) {
+  constexpr int IH = 2 * TOH + 1, IW = 2 * TOW + 1, CP = 32 + 8;  // conv2 input tile = conv1 outputs
+  constexpr int XH = IH + 2, XW = IW + 2;                          // net-input tile
+  constexpr int NT = 64 * NWAVE;
+  static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].stride == 2, "layer shapes");
+  __shared__ uint32_t xt[XH * XW];  // two bf16 channels per pixel
+  __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int n = blockIdx.x / tiles_per_img;
+  const int t = blockIdx.x % tiles_per_img;
+  const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
+  const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
+  const int xy0 = cy0 - 1, xx0 = cx0 - 1;          // net-input coordinates of xt (0, 0)
+
+  constexpr int NX = XH * XW, ITX = (NX + NT - 1) / NT;
+  const uint32_t* x32 = reinterpret_cast<const uint32_t*>(x);
+  uint32_t xr[ITX];
+#pragma unroll
+  for (int i = 0; i < ITX; ++i) {
+    const int e = min(tid + i * NT, NX - 1);
+    const int yy = xy0 + e / XW, xx = xx0 + e % XW;
+    const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
+    const uint32_t v = x32[((int64_t)n * g1.hi + (ok ? yy : 0)) * g1.wi + (ok ? xx : 0)];
+    xr[i] = ok ? v : 0u;
+  }
+  const bf16_t* wf1 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(0));
+  const float* b1 = reinterpret_cast<const float*>(blob + blob_bias_off(0));
+  bf16x8 bw[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) bw[nb] = ld8(wf1 + (nb * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+  for (int i = 0; i < ITX; ++i)
+    if (tid + i * NT < NX) xt[tid + i * NT] = xr[i];
+  __syncthreads();
+
+  constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16;
+  for (int blk = wv; blk < NBK; blk += NWAVE) {
+    const int pidx = blk * 16 + r16;
+    const int pi = min(pidx, NPX - 1);
+    const int py = pi / IW, px = pi % IW;
+    // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3
+    bf16_t v[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int tap = 4 * kg + j;
+      const uint32_t pair = tap < 9 ? xt[(py + tap / 3) * XW + px + tap % 3] : 0u;
+      v[2 * j] = (bf16_t)(pair & 0xFFFFu);
+      v[2 * j + 1] = (bf16_t)(pair >> 16);
+    }
+    const bf16x8 a = pack8(v);
+    const int cy = cy0 + py, cx = cx0 + px;
+    const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const f32x4 acc = mfma(bw[nb], a, f32x4{0.f, 0.f, 0.f, 0.f});
+      const int co = nb * 16 + 4 * kg;
+      const float4 bv = *reinterpret_cast<const float4*>(b1 + co);
+      uint2 pk = make_uint2(0u, 0u);
+      if (inside) {
+        pk.x = (uint32_t)f2bf(fmaxf(acc[0] + bv.x, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bv.y, 0.f)) << 16);
+        pk.y = (uint32_t)f2bf(fmaxf(acc[2] + bv.z, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bv.w, 0.f)) << 16);
+      }
+      if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
+    }
+  }
+  __syncthreads();
+  const bf16_t* wf2 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
+  const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
+  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW>(tile, wf2, b2, y, g2, n, oy0, ox0);
 }
 
 // ---------------------------------------------------------------------------
@@ -789,11 +901,30 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
     const uint8_t* a = f2.y;
     const int32_t p2 = (int32_t)f2.pitch;
     const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
+    // The 8 pixels read half-resolution columns k-1 .. k+4 (k = xb/2, clamped)
+    // of two rows: 12 loads instead of 32.  Pixel j's taps (up_tap) are
+    // columns (j+1)/2 and (j+1)/2 + 1 of that window; at the clamped image
+    // borders the tap weight of a substituted column is 0, so the values
+    // equal full_flow_at's.
+    const UpTap ty = up_tap(y, h);
+    const int32_t k0 = xb / 2 - 1;
+    float2 r0[6], r1[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int32_t col = min(max(k0 + c, 0), w - 1);
+      r0[c] = *reinterpret_cast<const float2*>(hp + ((int64_t)ty.i0 * w + col) * 2);
+      r1[c] = *reinterpret_cast<const float2*>(hp + ((int64_t)ty.i1 * w + col) * 2);
+    }
     float fu8[8], fv8[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int32_t x = xb + k;
-      const float2 f = full_flow_at(hp, x, y, h, w);
+      const UpTap tx = up_tap(x, w);
+      constexpr int kIa[8] = {0, 1, 1, 2, 2, 3, 3, 4};
+      const float2 fa = r0[kIa[k]], fb = r0[kIa[k] + 1], fc = r1[kIa[k]], fd = r1[kIa[k] + 1];
+      const float uu = (1.f - ty.f) * ((1.f - tx.f) * fa.x + tx.f * fb.x) + ty.f * ((1.f - tx.f) * fc.x + tx.f * fd.x);
+      const float vv = (1.f - ty.f) * ((1.f - tx.f) * fa.y + tx.f * fb.y) + ty.f * ((1.f - tx.f) * fc.y + tx.f * fd.y);
+      const float2 f = make_float2(2.f * uu, 2.f * vv);
       fu8[k] = f.x;
       fv8[k] = f.y;
       const float fu = floorf(f.x), fv = floorf(f.y);
@@ -965,12 +1096,17 @@ CGeom layer_geom(const NetDims& d, int l, int64_t n) {
 constexpr int kMR = 2;  // 16-pixel row blocks per wave
 
 // Output tile (rows x columns), waves per workgroup and weights-in-LDS choice
-// of the LDS-tiled forward kernel per layer: conv5 and conv6 (few output
-// channels, small weights) keep the whole weight tensor in LDS next to a
-// 16 x 32 output tile.
+// of the LDS-tiled forward kernel per layer (measured on the 1080p batch):
+// conv4, conv5 and conv6 keep the whole weight tensor in LDS (conv4's 110 KB
+// next to its quarter-size upsampled input tile); conv6 uses a 16 x 32
+// output tile with 8 waves, conv4 8 x 32 with 8 waves (two pixel blocks per
+// wave keep it at two waves per SIMD), conv3 4 x 16 with 2 waves (its
+// stride-2 input tile would otherwise hold the CU's LDS alone), the others
+// 8 x 32 (4 x 32 for stride 2) with 4 waves.
 template <int L> struct FwdTile {
-  static constexpr bool BLDS = (L == 4 || L == 5);
-  static constexpr int TOH = kNet[L].stride == 2 ? 4 : (BLDS ? 16 : 8), TOW = 32, NWAVE = BLDS ? 8 : 4;
+  static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
+  static constexpr int TOH = kNet[L].stride == 2 ? 4 : (L == 5 ? 16 : 8), TOW = L == 2 ? 16 : 32;
+  static constexpr int NWAVE = (L == 5 || L == 3) ? 8 : (L == 2 ? 2 : 4);
 };
 
 constexpr const char* kFwdTimer[kLayers] = {"conv_fwd1", "conv_fwd2", "conv_fwd3", "conv_fwd4", "conv_fwd5",
@@ -1027,6 +1163,32 @@ scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float
   return SCN_OK;
 }
 
+scn_status launch_conv12(const bf16_t* x, const uint8_t* blob, bf16_t* y, const NetDims& d, int64_t n,
+                          hipStream_t s) {
+  constexpr int TOH = FwdTile<1>::TOH, TOW = FwdTile<1>::TOW, NW = FwdTile<1>::NWAVE;
+  const CGeom g1 = layer_geom(d, 0, n), g2 = layer_geom(d, 1, n);
+  const int32_t tx = (g2.wo + TOW - 1) / TOW, ty = (g2.ho + TOH - 1) / TOH;
+  const int64_t grid = (int64_t)tx * ty * n;
+  if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+  KernelTimer timer("conv_fwd", s);
+  KernelTimer timer_l("conv_fwd12", s);
+  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y, g1, g2, tx,
+                     tx * ty);
+  SCN_LAUNCHED("fused conv1 + conv2 launch");
+  return SCN_OK;
+}
+
+// Inference forward: conv1 and conv2 fused (conv1's activation is not kept).
+scn_status net_forward_infer(const NetDims& d, int64_t n, const uint8_t* blob, const NetBuffers& b, hipStream_t s) {
+  scn_status st;
+  if ((st = launch_conv12(b.x, blob, b.act[1], d, n, s)) != SCN_OK) return st;
+  if ((st = launch_fwd<2>(b.act[1], blob, b.act[2], layer_geom(d, 2, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<3>(b.act[2], blob, b.act[3], layer_geom(d, 3, n), s)) != SCN_OK) return st;
+  if ((st = launch_fwd<4>(b.act[3], blob, b.act[4], layer_geom(d, 4, n), s)) != SCN_OK) return st;
+  return launch_fwd<5>(b.act[4], blob, b.half, layer_geom(d, 5, n), s);
+}
+
+// Training forward: every activation is kept for the backward pass.
 scn_status net_forward(const NetDims& d, int64_t n, const uint8_t* blob, const NetBuffers& b, hipStream_t s) {
   scn_status st;
   if ((st = launch_fwd<0>(b.x, blob, b.act[0], layer_geom(d, 0, n), s)) != SCN_OK) return st;
@@ -1253,7 +1415,7 @@ scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* 
   const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
   const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
   if ((st = sg::launch_net_input(frames, pairs, b.x, d, ch.n_pairs, s)) != SCN_OK) return st;
-  if ((st = sg::net_forward(d, ch.n_pairs, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+  if ((st = sg::net_forward_infer(d, ch.n_pairs, (const uint8_t*)net, b, s)) != SCN_OK) return st;
   return sg::launch_flow_up(b.half, pairs, d, ch.n_pairs, s);
 }
 
@@ -1286,7 +1448,7 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
       const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
       const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
       if ((st = sg::launch_net_input(frames, pairs, b.x, d, n, s)) != SCN_OK) return st;
-      if ((st = sg::net_forward(d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+      if ((st = sg::net_forward_infer(d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
       if ((st = sg::launch_up_gate(b.half, frames, pairs, gpart, d, n, gate_tau, active, s)) != SCN_OK) return st;
       const int64_t fw = (ch.n_frames + 3) / 4;
       hipLaunchKernelGGL(sg::k_zero_bytes, dim3((unsigned)((fw + 255) / 256)), dim3(256), 0, s, (uint32_t*)factive,

@@ -72,9 +72,11 @@ def test_param_layout_matches_oracle():
     assert scn.net_params() == S.n_params()
 
 
-def test_forward_parity():
+@pytest.mark.parametrize("W,H", [(64, 48), (208, 136)])
+def test_forward_parity(W, H):
+    """Inference forward (conv1 + conv2 fused, LDS-tiled layers) against the
+    oracle; 208 x 136 spans several ragged tiles of every layer."""
     need_gpu()
-    W, H = 64, 48
     tab, job = _pairs_table(W, H, 4, 11)
     master, p64 = _master(_params(1))
     net = scn.net_pack(master)
