@@ -81,12 +81,17 @@ def _read_tune_cache():
     return [line.split() for line in open(path) if line.strip()]
 
 
+def _layer_flops(W, H):
+    """Algorithmic FLOP of each surrogate layer for one pair at full resolution W x H."""
+    h, w = H // 2, W // 2
+    dims = [(h, w, 2, 32), (h // 2, w // 2, 32, 64), (h // 4, w // 4, 64, 96), (h // 2, w // 2, 96, 64),
+            (h, w, 64, 32), (h, w, 32, 2)]
+    return [2 * 9 * ci * co * ho * wo for ho, wo, ci, co in dims]
+
+
 def _conv_flops(W, H):
     """FLOP of one surrogate forward at full resolution W x H (half-resolution network)."""
-    h, w = H // 2, W // 2
-    dims = [(h, w, 2, 32, 1), (h // 2, w // 2, 32, 64, 1), (h // 4, w // 4, 64, 96, 1), (h // 2, w // 2, 96, 64, 1),
-            (h, w, 64, 32, 1), (h, w, 32, 2, 1)]
-    return sum(2 * 9 * ci * co * ho * wo for ho, wo, ci, co, _ in dims)
+    return sum(_layer_flops(W, H))
 
 
 def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_total, args):
@@ -121,13 +126,20 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     dt = time.perf_counter() - t0
     conv_ms, conv_n = scn.timing_read("conv_fwd")
     per_layer = {}
+    lf = _layer_flops(W, H)
+    layer_tflops = {}
     for li in (1, 2, 12, 3, 4, 5, 6):
         ms, n_l = scn.timing_read("conv_fwd%d" % li)
         if n_l:
-            per_layer["conv%d" % li if li != 12 else "conv1+2 (fused)"] = ms / args.steps
+            name = "conv%d" % li if li != 12 else "conv1+2 (fused)"
+            per_layer[name] = ms / args.steps
+            fl = (lf[0] + lf[1]) if li == 12 else lf[li - 1]
+            n_pairs_all = sum(f.shape[0] for f in plain_flows)
+            layer_tflops[name] = fl * n_pairs_all * args.steps / (ms * 1e-3) / 1e12
     gate_ms, _ = scn.timing_read("gate")
     up_ms, _ = scn.timing_read("flow_up")
-    fb_ms = {k: scn.timing_read(k)[0] / args.steps for k in ["pyr_down", "hs_setup", "hs_jacobi"]}
+    fb_ms = {k: scn.timing_read(k)[0] / args.steps for k in ["pyr_down", "hs_setup", "hs_jacobi"] +
+             ["hs_jacobi_l%d" % l for l in range(LEVELS)]}
     scn.timing_enable(False)
     n_pairs = sum(f.shape[0] for f in plain_flows)
     epe = torch.cat([torch.sqrt(((o - p) ** 2).sum(dim=1)).mean(dim=(1, 2)) for o, p in zip(outs, plain_flows)])
@@ -144,7 +156,9 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
                                       **{"fallback_" + k: v for k, v in fb_ms.items()}},
             "mfma": {"achieved_TFLOPs": mfma_tflops, "peak_TFLOPs": BF16_PEAK_TFLOPS,
                      "utilisation": mfma_tflops / BF16_PEAK_TFLOPS, "conv_fwd_ms": conv_ms,
-                     "flop_per_1080p_pair": _conv_flops(W, H)},
+                     "flop_per_1080p_pair": _conv_flops(W, H),
+                     "per_layer_TFLOPs": layer_tflops,
+                     "per_layer_utilisation": {k: v / BF16_PEAK_TFLOPS for k, v in layer_tflops.items()}},
             "weights": os.path.relpath(path, ROOT), "train_meta": {k: meta[k] for k in meta if k != "loss_history"}}
 
 
@@ -171,7 +185,7 @@ def _timed_calls(torch, calls, steps, warmup):
         for c in calls:
             c()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    return (time.perf_counter() - t0) / max(steps, 1)
 
 
 def c3_workload(scn, torch, dev, args):
@@ -204,45 +218,76 @@ def c3_workload(scn, torch, dev, args):
     resident_gb = sum(t.numel() for t in keep) / 1e9
     per_call = C3_STREAMS_PER_RES // 4
     mixed = [[jobs[(r, 4 * q + i)] for r in range(len(C3_RES)) for i in range(per_call)] for q in range(4)]
+    # ring slot r * per_call + i holds the output of the i-th resolution-r job of a call
     ring = [torch.empty((scn.count_pairs(j), 2, j.table.height, j.table.width), dtype=torch.float32, device=dev)
             for j in mixed[0]]
+    hists = {key: torch.empty((scn.count_rows(j), 3, 16), dtype=torch.int32, device=dev) for key, j in jobs.items()}
+    ws_hist = {key: torch.empty(scn.workspace_bytes(scn.SCN_OP_HIST, [j]), dtype=torch.uint8, device=dev)
+               for key, j in jobs.items()}
+    # one workspace per call, so that every call's plan stays uploaded (a
+    # captured graph replays without host copies)
     ws_bytes = int(args.c3_ws_gb * (1 << 30))
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    def _call(js, slots):
-        outs = [ring[k] for k in slots]
-        return lambda: scn.flow(js, prm, outs=outs, stream=stream, ws=ws, ws_bytes=ws_bytes)
+    wss = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(4)]
+    key_of = {id(j): key for key, j in jobs.items()}
 
-    # ring slot r * per_call + i holds the output of the i-th resolution-r job of a call
-    calls = [_call(js, range(len(js))) for js in mixed]
+    def _call(js, slots, ws):
+        outs = [ring[k] for k in slots]
+
+        def run():
+            for j in js:
+                k = key_of[id(j)]
+                scn.hist(j, out=hists[k], stream=torch.cuda.current_stream(), ws=ws_hist[k])
+            scn.flow(js, prm, outs=outs, stream=torch.cuda.current_stream(), ws=ws, ws_bytes=ws_bytes)
+        return run
+
+    calls = [_call(js, range(len(js)), wss[q]) for q, js in enumerate(mixed)]
+    _timed_calls(torch, calls, 0, args.warmup)  # warm-up: plans, autotuning of new shapes
     scn.timing_enable(True, 1 << 20)
     scn.timing_reset()
-    dt = _timed_calls(torch, calls, args.steps, args.warmup)
+    dt_eager = _timed_calls(torch, calls, args.steps, 0)
     jac_ms, jac_n = scn.timing_read("hs_jacobi")
+    hist_ms, _ = scn.timing_read("hist16")
     scn.timing_enable(False)
+    # the whole step (4 x (16 HIST + one flow call)) captured once, replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for c in calls:
+                c()
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
     frames = sum(scn.count_rows(j) for j in jobs.values())
     pairs = sum(scn.count_pairs(j) for j in jobs.values())
     px_sweeps = sum(scn.count_pairs(j) * _px_levels(j.table.width, j.table.height, LEVELS)
                     for j in jobs.values()) * ITERS
-    jac_steps = args.steps + args.warmup
     per_res = {}
     for r, (w, h) in enumerate(C3_RES):
-        rc = [_call([jobs[(r, 4 * q + i)] for i in range(per_call)], [r * per_call + i for i in range(per_call)])
-              for q in range(4)]
+        rc = [_call([jobs[(r, 4 * q + i)] for i in range(per_call)], [r * per_call + i for i in range(per_call)],
+                    wss[0]) for q in range(4)]
         t = _timed_calls(torch, rc, 1, 1)
         fr = sum(scn.count_rows(jobs[(r, k)]) for k in range(C3_STREAMS_PER_RES))
         pr = sum(scn.count_pairs(jobs[(r, k)]) for k in range(C3_STREAMS_PER_RES))
-        per_res["%dx%d" % (w, h)] = {"frames_per_s": fr / t, "pairs_per_s": pr / t, "s_per_pass": t}
-    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * jac_steps / (jac_ms * 1e-3) / 1e12
-    return {"metric": "frames/s through flow, 64 uneven streams (C3)", "value": frames / dt, "unit": "frames/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        per_res["%dx%d" % (w, h)] = {"frames_per_s": fr / t, "pairs_per_s": pr / t,
+                                      "latency_s_per_window": t / C3_STREAMS_PER_RES, "s_per_pass": t}
+    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * args.steps / (jac_ms * 1e-3) / 1e12
+    return {"metric": "frames/s through HIST + flow, 64 uneven streams (C3)", "value": frames / dt,
+            "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "64 streams: 16 each at 640x360, 1280x720, 1920x1080, 3840x2160; one 240-row "
-                                   "RANGE window per stream (seeds 3000+s) in a 2400-row table; Horn-Schunck "
-                                   "L=%d alpha=%g %d iters; 4 batched calls of 16 mixed-resolution jobs per step"
-                                   % (LEVELS, ALPHA, ITERS),
+                                   "RANGE window per stream (seeds 3000+s) in a 2400-row table; HIST + Horn-Schunck "
+                                   "L=%d alpha=%g %d iters; one captured graph per step: 4 calls of 16 "
+                                   "mixed-resolution jobs" % (LEVELS, ALPHA, ITERS),
                        "frames_per_step": frames, "pairs_per_step": pairs, "resident_nv12_GB": resident_gb,
-                       "workspace_GB": ws_bytes / 2 ** 30, "generation_s": gen_s},
-            "pairs_per_s": pairs / dt,
+                       "workspace_GB_per_call": ws_bytes / 2 ** 30, "generation_s": gen_s},
+            "pairs_per_s": pairs / dt, "eager_ms_per_step": dt_eager * 1e3, "hist_ms_per_step": hist_ms / args.steps,
             "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None},
             "per_resolution": per_res}
@@ -270,29 +315,63 @@ def c5_workload(scn, torch, dev, args):
     jobs = [scn.Job(tab, scn.Sampling.range([(t * cams, (t + 1) * cams) for t in range(t0, t0 + per_call_t)]))
             for t0 in range(0, steps_t, per_call_t)]
     ring = torch.empty((scn.count_pairs(jobs[0]), 2, S, S), dtype=torch.float32, device=dev)
+    hist = torch.empty((scn.count_rows(jobs[0]), 3, 16), dtype=torch.int32, device=dev)
+    ws_h = torch.empty(scn.workspace_bytes(scn.SCN_OP_HIST, [jobs[0]]), dtype=torch.uint8, device=dev)
     ws_bytes = int(args.c3_ws_gb * (1 << 30))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    calls = [(lambda j=j: scn.flow([j], prm, outs=[ring], stream=stream, ws=ws, ws_bytes=ws_bytes)) for j in jobs]
+
+    def plain(j):
+        scn.hist(j, out=hist, stream=stream, ws=ws_h)
+        scn.flow([j], prm, outs=[ring], stream=stream, ws=ws, ws_bytes=ws_bytes)
+    calls = [(lambda j=j: plain(j)) for j in jobs]
+    _timed_calls(torch, calls, 0, args.warmup)  # warm-up (includes the Jacobi autotuning of new shapes)
     scn.timing_enable(True, 1 << 20)
     scn.timing_reset()
-    dt = _timed_calls(torch, calls, args.steps, args.warmup)
+    dt = _timed_calls(torch, calls, args.steps, 0)
     jac_ms, _ = scn.timing_read("hs_jacobi")
     scn.timing_enable(False)
     pairs = sum(scn.count_pairs(j) for j in jobs)
     frames = cams * steps_t
     px_sweeps = pairs * _px_levels(S, S, levels) * ITERS
-    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * (args.steps + args.warmup) / (jac_ms * 1e-3) / 1e12
-    return {"metric": "rig frames/s through flow (C5)", "value": frames / dt, "unit": "frames/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "14-camera rig x 300 steps at 2048x2048, 13 chain pairs per step (RANGE "
-                                   "windows of 14 rows), Horn-Schunck L=5 alpha=%g %d iters; 5 calls of 780 "
-                                   "pairs per step" % (ALPHA, ITERS),
+    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * args.steps / (jac_ms * 1e-3) / 1e12
+    # surrogate + gated fallback on the same calls (trained on 512x384 layered scenes)
+    sur = None
+    from paper_1805_07339_amd import train as T
+    if not args.no_surrogate and os.path.exists(args.weights or T.DEFAULT_WEIGHTS):
+        master, meta = T.load(args.weights or T.DEFAULT_WEIGHTS, dev)
+        net = scn.net_pack(master)
+        tau = float(meta.get("tau", 0.0)) if args.tau is None else args.tau
+        ring_s = torch.empty_like(ring)
+        fb = torch.empty(ring.shape[0], dtype=torch.uint8, device=dev)
+        res = torch.empty(ring.shape[0], dtype=torch.float32, device=dev)
+
+        def surr(j):
+            scn.hist(j, out=hist, stream=stream, ws=ws_h)
+            scn.flow_surrogate([j], net, tau, prm, outs=[ring_s], fell_back=[fb], residual=[res], stream=stream,
+                               ws=ws, ws_bytes=ws_bytes)
+        scalls = [(lambda j=j: surr(j)) for j in jobs]
+        _timed_calls(torch, scalls, 0, args.warmup)
+        dts = _timed_calls(torch, scalls, args.steps, 0)
+        # EPE against plain flow and fallback rate on the last call's pairs
+        plain(jobs[-1])
+        surr(jobs[-1])
+        torch.cuda.synchronize()
+        epe = torch.stack([torch.sqrt(((ring_s[k] - ring[k]) ** 2).sum(dim=0)).mean() for k in range(ring.shape[0])])
+        sur = {"value": frames / dts, "unit": "frames/s", "ms_per_step": dts * 1e3, "tau": tau,
+               "fallback_rate_last_call": float(fb.float().mean()), "mean_epe_vs_plain_px_last_call": float(epe.mean()),
+               "pairs_in_epe": int(ring.shape[0])}
+    return {"metric": "rig frames/s through HIST + flow (C5)", "value": frames / dt, "unit": "frames/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "14-camera rig x 300 steps at 2048x2048, HIST of every frame and flow of the 13 "
+                                   "chain pairs per step (RANGE windows of 14 rows), Horn-Schunck L=5 alpha=%g %d "
+                                   "iters; 5 calls of 840 frames / 780 pairs per step" % (ALPHA, ITERS),
                        "frames_per_step": frames, "pairs_per_step": pairs, "resident_nv12_GB": rows.numel() / 1e9,
                        "workspace_GB": ws_bytes / 2 ** 30, "generation_s": gen_s},
             "pairs_per_s": pairs / dt,
             "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None}}
+                         "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None},
+            "surrogate": sur}
 
 
 def summarize_rocprof(directory: str, bench_json: str = None) -> str:
@@ -352,14 +431,18 @@ def summarize_rocprof(directory: str, bench_json: str = None) -> str:
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hs_jacobi_traffic_1080p_stride24_gather1.txt")
 
 
-def _flow_source_hash() -> str:
-    """sha256 of the Jacobi kernels' source (the counters describe this code)."""
+def _source_hash(files=("flow.hip", "tune.inc")) -> str:
+    """sha256 of kernel sources (the counters describe this code)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("flow.hip", "tune.inc"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1805_07339_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def _flow_source_hash() -> str:
+    return _source_hash(("flow.hip", "tune.inc"))
 
 
 def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
@@ -394,10 +477,18 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         res[ctr] = (factor, copy, sum(jac) * 1024.0 * factor, len(jac))
     fb, wb = res["FETCH_SIZE"][2], res["WRITE_SIZE"][2]
     alg = info["roofline"]["px_sweeps"] * 28.0
+    # the large HIST and conversion launches (the largest dispatch of each kernel)
+    big = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        factor = res[ctr][0]
+        for kname in ("k_hist16", "k_nv12_rgb24"):
+            vals = [v for _, n, v in rows(d) if kname in n]
+            big[(kname, ctr)] = max(vals) * 1024.0 * factor if vals else 0.0
     lines = [
         "# HBM traffic of the Jacobi launches of one timed step (1080p STRIDE-24 + GATHER 1%%, %d pairs)"
         % info["config"]["pairs_per_step"],
         "# source sha256(flow.hip + tune.inc) = %s" % _flow_source_hash(),
+        "# colour source sha256(color.hip) = %s" % _source_hash(("color.hip",)),
         "# commands (from the repository root, cd /tmp && export TMPDIR=/tmp first):",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o run -- python3 bench.py --steps 1 --warmup 1 "
         "--no-cpu-baseline --no-surrogate --calib-copy",
@@ -411,24 +502,44 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         "traffic_bytes_per_launch %.0f" % ((fb + wb) / n_launch),
         "streaming_algorithmic_bytes_per_step %.0f  (28 B per pixel-sweep)" % alg,
         "traffic_over_streaming_algorithmic %.4f" % ((fb + wb) / alg),
+        "hist_bytes_per_launch %.0f  (%d frames; algorithmic %.0f)" % (
+            big[("k_hist16", "FETCH_SIZE")] + big[("k_hist16", "WRITE_SIZE")], info["hist"]["frames_per_launch"],
+            info["hist"]["algorithmic_bytes_per_frame"] * info["hist"]["frames_per_launch"]),
+        "convert_bytes_per_launch %.0f  (%d frames; algorithmic %.0f)" % (
+            big[("k_nv12_rgb24", "FETCH_SIZE")] + big[("k_nv12_rgb24", "WRITE_SIZE")],
+            info["convert_rgb24"]["frames_per_launch"], 4.5 * W * H * info["convert_rgb24"]["frames_per_launch"]),
     ]
     return "\n".join(lines)
+
+
+def read_counter_summary():
+    """Values of the committed counter summary (HBM bytes per launch), and
+    whether it describes the current Jacobi source."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return {}, False
+    kv = {}
+    src = csrc = None
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("# source sha256"):
+            src = line.split("=")[-1].strip()
+        elif line.startswith("# colour source sha256"):
+            csrc = line.split("=")[-1].strip()
+        elif not line.startswith("#") and line.strip():
+            k, v = line.split()[:2]
+            kv[k] = float(v)
+    if csrc != _source_hash(("color.hip",)):  # HIST / conversion counters describe older colour kernels
+        kv.pop("hist_bytes_per_launch", None)
+        kv.pop("convert_bytes_per_launch", None)
+    return kv, src == _flow_source_hash()
 
 
 def read_traffic():
     """Measured HBM bytes per Jacobi launch, if the committed counter summary
     describes the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+    kv, current = read_counter_summary()
+    if not kv:
         return None, "no counter summary"
-    kv = {}
-    src = None
-    for line in open(TRAFFIC_PROFILE):
-        if line.startswith("# source sha256"):
-            src = line.split("=")[-1].strip()
-        elif not line.startswith("#") and line.strip():
-            k, v = line.split()[:2]
-            kv[k] = float(v)
-    if src != _flow_source_hash():
+    if not current:
         return None, "counter summary predates the current Jacobi source"
     return kv.get("traffic_bytes_per_launch"), os.path.relpath(TRAFFIC_PROFILE, ROOT)
 
@@ -452,7 +563,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2",
                     help="c2: the 1080p sampled-stream step (default); c3: 64 uneven streams; c5: camera rig")
-    ap.add_argument("--c3-ws-gb", type=float, default=32.0, help="flow workspace for --workload c3/c5 (GiB)")
+    ap.add_argument("--c3-ws-gb", type=float, default=16.0,
+                    help="flow workspace per call for --workload c3 / c5 (GiB)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
@@ -521,6 +633,7 @@ def main():
 
     # --- algorithmic work of the dominant kernel (Jacobi) -------------------
     traffic, traffic_src = read_traffic()
+    ctr_kv, _ = read_counter_summary()  # HIST / conversion bytes (kept only while color.hip matches)
     from oracle.hs import level_sizes
     lv = level_sizes(W, H, LEVELS)
     px_levels = sum(w * h for w, h in lv)
@@ -591,10 +704,16 @@ def main():
         "kernels": {k: {"ms_total": v[0], "launches": v[1]} for k, v in kern.items()},
         "hist": {"achieved_GBps": hist_gbs, "frac": hist_gbs / HBM_PEAK_GBS, "avg_launch_ms": hist_ms / max(hist_n, 1),
                  "frames_per_launch": n_big, "algorithmic_bytes_per_frame": 1.5 * W * H + 192,
-                 "frames_per_s": n_big * hist_n / (hist_ms * 1e-3)},
+                 "frames_per_s": n_big * hist_n / (hist_ms * 1e-3),
+                 "counter_GBps": (ctr_kv["hist_bytes_per_launch"] / (hist_ms / max(hist_n, 1) * 1e-3) / 1e9
+                                  if "hist_bytes_per_launch" in ctr_kv else None)},
         "convert_rgb24": {"achieved_GBps": conv_gbs, "frac": conv_gbs / HBM_PEAK_GBS,
-                          "avg_launch_ms": conv_ms / max(conv_n, 1), "frames_per_launch": 400},
+                          "avg_launch_ms": conv_ms / max(conv_n, 1), "frames_per_launch": 400,
+                          "counter_GBps": (ctr_kv["convert_bytes_per_launch"] / (conv_ms / max(conv_n, 1) * 1e-3) / 1e9
+                                           if "convert_bytes_per_launch" in ctr_kv else None)},
         "surrogate": surrogate,
+        "surrogate_over_plain_frames_per_s": (surrogate["value"] / (m_total * args.steps / dt)
+                                              if surrogate and "value" in surrogate else None),
         "tune_cache": _read_tune_cache(),
         "paper_context": "Scanner reports HIST on a 202,525-frame 1080p film incl. H.264 decode: 4.3 min on a "
                          "32-vCPU GCE instance, ~15 min on one K80 (Sec. 5.1.4); no HS/flow absolute numbers.",

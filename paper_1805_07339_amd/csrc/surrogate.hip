@@ -151,8 +151,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
       } else {
         static_assert(L == kLayers - 1 || CO % 4 == 0, "epilogue stores 4 channels per lane");
         uint2 pk;
-        pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
-        pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
+        pk.x = pack_bf16x2(v0, v1);
+        pk.y = pack_bf16x2(v2, v3);
         *reinterpret_cast<uint2*>(reinterpret_cast<bf16_t*>(y) + m * CO + co) = pk;
       }
     }
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // global).  Each wave owns 16 * MR output pixels (MR pixel blocks of 16 along
 // a row) x all output channels; the epilogue adds the bias, applies ReLU and
 // stores 4 consecutive channels per lane.
-template <int L, int TOH, int TOW, int NWAVE, int SH, int SW>
+template <int L, int TOH, int TOW, int NWAVE, int SH, int SW, bool WLDS>
 __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, const bf16_t* __restrict__ wf,
                                               const float* __restrict__ bias, void* __restrict__ y, const CGeom& g,
                                               int n, int oy0, int ox0) {
@@ -191,8 +191,11 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
   constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
+  const uint32_t blane = 2u * (uint32_t)(r16 * CI + kg * 8);  // lane's byte offset in a fragment row block
   auto bfrag = [&](int tap, int nb, int cb) -> bf16x8 {
-    return ld8(wf + (tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8);
+    const bf16_t* base = wf + (tap * COP + nb * 16) * CI + cb * 32;  // wave-uniform
+    if constexpr (WLDS) return ld8(base + (r16 * CI + kg * 8));
+    else return ldg32(reinterpret_cast<const bf16x8*>(base), blane);
   };
   f32x4 acc[MR][NB];
 #pragma unroll
@@ -200,10 +203,8 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   if constexpr (S == 1) {
-    // Stride 1: the fragment of tap (ky, kx+1) is the tap (ky, kx) fragment of
-    // the next pixel, i.e. the next lane of the 16-lane row.  Read the kx = 0
-    // fragment once, plus pixels 16 and 17 of the block in lanes 0 and 1, and
-    // rotate within rows (DPP row_ror) for kx = 1, 2.
+    // Stride 1: the three taps of a tap row read consecutive pixels of one
+    // tile row (one 16-byte LDS read per tap and pixel block).
     constexpr int NST = 3 * NCB;  // steps: (ky, channel block)
     bf16x8 bq[2][3][NB];
 #pragma unroll
@@ -226,24 +227,9 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
         const int orow = blk / BPR, c0 = (blk % BPR) * 16;
         auto ti = [](int e) { return UP ? (e + 1) >> 1 : e; };  // effective -> stored tile index
         const bf16_t* rowp = tile + (ti(orow + ky) * SW) * CP + cb * 32 + kg * 8;
-        const bf16x8 f0 = ld8(rowp + ti(c0 + r16) * CP);
-        bf16x8 gx = f0;
-        if (r16 < 2) gx = ld8(rowp + ti(c0 + 16 + r16) * CP);
-        const uint4 u0 = __builtin_bit_cast(uint4, f0), ug = __builtin_bit_cast(uint4, gx);
-        const uint4 t1 = r16 == 0 ? ug : u0;  // lane 0 carries pixel 16
-        const uint4 t2 = r16 < 2 ? ug : u0;   // lanes 0, 1 carry pixels 16, 17
-        uint4 s1, s2;
-        s1.x = __builtin_amdgcn_update_dpp(0u, t1.x, 0x12F, 0xf, 0xf, false);  // row_ror:15
-        s1.y = __builtin_amdgcn_update_dpp(0u, t1.y, 0x12F, 0xf, 0xf, false);
-        s1.z = __builtin_amdgcn_update_dpp(0u, t1.z, 0x12F, 0xf, 0xf, false);
-        s1.w = __builtin_amdgcn_update_dpp(0u, t1.w, 0x12F, 0xf, 0xf, false);
-        s2.x = __builtin_amdgcn_update_dpp(0u, t2.x, 0x12E, 0xf, 0xf, false);  // row_ror:14
-        s2.y = __builtin_amdgcn_update_dpp(0u, t2.y, 0x12E, 0xf, 0xf, false);
-        s2.z = __builtin_amdgcn_update_dpp(0u, t2.z, 0x12E, 0xf, 0xf, false);
-        s2.w = __builtin_amdgcn_update_dpp(0u, t2.w, 0x12E, 0xf, 0xf, false);
-        a0[mr] = f0;
-        a1[mr] = __builtin_bit_cast(bf16x8, s1);
-        a2[mr] = __builtin_bit_cast(bf16x8, s2);
+        a0[mr] = ld8(rowp + ti(c0 + r16) * CP);
+        a1[mr] = ld8(rowp + ti(c0 + r16 + 1) * CP);
+        a2[mr] = ld8(rowp + ti(c0 + r16 + 2) * CP);
       }
 #pragma unroll
       for (int kx = 0; kx < 3; ++kx)
@@ -280,12 +266,14 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
     }
   }
   // lane (r16, kg) holds channels nb*16 + 4kg .. +3 of pixel r16 of each block
+  constexpr int OBYTES = L == kLayers - 1 ? 4 : 2;  // FP32 flow or BF16 activation
+  char* yimg = reinterpret_cast<char*>(y) + (int64_t)n * g.ho * g.wo * CO * OBYTES;  // wave-uniform
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr) {
     const int blk = wv * MR + mr;
     const int oy = oy0 + blk / BPR, ox = ox0 + (blk % BPR) * 16 + r16;
     if (oy >= g.ho || ox >= g.wo) continue;
-    const int64_t m = ((int64_t)n * g.ho + oy) * g.wo + ox;
+    const uint32_t mo = (uint32_t)(oy * g.wo + ox) * (uint32_t)(CO * OBYTES);  // pixel's byte offset in the image
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int co = nb * 16 + 4 * kg;
@@ -300,12 +288,13 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
       }
       if constexpr (L == kLayers - 1) {
         static_assert(CO == 2, "last layer writes (u, v)");
-        if (co == 0) *reinterpret_cast<float2*>(reinterpret_cast<float*>(y) + m * CO) = make_float2(v0, v1);
+        if (co == 0) stg32(reinterpret_cast<f32x2_t*>(yimg), mo, f32x2_t{v0, v1});
       } else {
         uint2 pk;
-        pk.x = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
-        pk.y = (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16);
-        *reinterpret_cast<uint2*>(reinterpret_cast<bf16_t*>(y) + m * CO + co) = pk;
+        pk.x = pack_bf16x2(v0, v1);
+        pk.y = pack_bf16x2(v2, v3);
+        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+        stg32(reinterpret_cast<u32x2_t*>(yimg), mo + 2u * (uint32_t)co, u32x2_t{pk.x, pk.y});
       }
     }
   }
@@ -349,6 +338,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
 #pragma unroll
   for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
   uint4 treg[IT];
+  const bf16_t* ximg = x + (int64_t)n * g.hi * g.wi * CI;  // this image's input (wave-uniform)
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = min(tid + i * NT, NE - 1);
@@ -357,8 +347,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
     const int yy = (UP ? (iy0 >> 1) : iy0) + p / SW, xx = (UP ? (ix0 >> 1) : ix0) + p % SW;
     const bool ok = yy >= 0 && yy < g.hi && xx >= 0 && xx < g.wi;
     const int sy = ok ? yy : 0, sx = ok ? xx : 0;
-    const uint4 v = *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.hi + sy) * g.wi + sx) * CI + ch * 8);
-    treg[i] = ok ? v : make_uint4(0, 0, 0, 0);
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    const u32x4_t v = ldg32(reinterpret_cast<const u32x4_t*>(ximg), 2u * (uint32_t)((sy * g.wi + sx) * CI + ch * 8));
+    treg[i] = ok ? make_uint4(v.x, v.y, v.z, v.w) : make_uint4(0, 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < WIT; ++i)
@@ -371,7 +362,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
   __syncthreads();
 
   const bf16_t* wf = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
-  conv_tile_mma<L, TOH, TOW, NWAVE, SH, SW>(tile, wf, bias, y, g, n, oy0, ox0);
+  conv_tile_mma<L, TOH, TOW, NWAVE, SH, SW, BLDS>(tile, wf, bias, y, g, n, oy0, ox0);
 }
 
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
@@ -421,32 +412,45 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict_
     if (tid + i * NT < NX) xt[tid + i * NT] = xr[i];
   __syncthreads();
 
-  constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16;
-  for (int blk = wv; blk < NBK; blk += NWAVE) {
+  // per lane: the xt offsets of its four taps (lane group kg covers taps
+  // 4kg .. 4kg+3 of K = 18 = 9 taps x 2 channels; taps >= 9 are zero) and
+  // the biases of its output channels
+  int toff[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int tap = 4 * kg + j;
+    toff[j] = tap < 9 ? (tap / 3) * XW + tap % 3 : -1;
+  }
+  float4 bv[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) bv[nb] = *reinterpret_cast<const float4*>(b1 + nb * 16 + 4 * kg);
+  constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16, NIT = (NBK + NWAVE - 1) / NWAVE;
+  // unrolled: the LDS reads and MFMAs of successive pixel blocks overlap
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int blk = wv + it * NWAVE;
+    if (blk >= NBK) break;
     const int pidx = blk * 16 + r16;
     const int pi = min(pidx, NPX - 1);
     const int py = pi / IW, px = pi % IW;
-    // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3
-    bf16_t v[8];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int tap = 4 * kg + j;
-      const uint32_t pair = tap < 9 ? xt[(py + tap / 3) * XW + px + tap % 3] : 0u;
-      v[2 * j] = (bf16_t)(pair & 0xFFFFu);
-      v[2 * j + 1] = (bf16_t)(pair >> 16);
-    }
-    const bf16x8 a = pack8(v);
+    // each xt word is a tap's two channels already packed (channel 0 low)
+    uint4 pw;
+    const int pb = py * XW + px;
+    pw.x = toff[0] >= 0 ? xt[pb + toff[0]] : 0u;
+    pw.y = toff[1] >= 0 ? xt[pb + toff[1]] : 0u;
+    pw.z = toff[2] >= 0 ? xt[pb + toff[2]] : 0u;
+    pw.w = toff[3] >= 0 ? xt[pb + toff[3]] : 0u;
+    const bf16x8 a = __builtin_bit_cast(bf16x8, pw);
     const int cy = cy0 + py, cx = cx0 + px;
     const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const f32x4 acc = mfma(bw[nb], a, f32x4{0.f, 0.f, 0.f, 0.f});
       const int co = nb * 16 + 4 * kg;
-      const float4 bv = *reinterpret_cast<const float4*>(b1 + co);
       uint2 pk = make_uint2(0u, 0u);
       if (inside) {
-        pk.x = (uint32_t)f2bf(fmaxf(acc[0] + bv.x, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1] + bv.y, 0.f)) << 16);
-        pk.y = (uint32_t)f2bf(fmaxf(acc[2] + bv.z, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3] + bv.w, 0.f)) << 16);
+        pk.x = pack_bf16x2(fmaxf(acc[0] + bv[nb].x, 0.f), fmaxf(acc[1] + bv[nb].y, 0.f));
+        pk.y = pack_bf16x2(fmaxf(acc[2] + bv[nb].z, 0.f), fmaxf(acc[3] + bv[nb].w, 0.f));
       }
       if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
     }
@@ -454,7 +458,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict_
   __syncthreads();
   const bf16_t* wf2 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
   const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
-  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW>(tile, wf2, b2, y, g2, n, oy0, ox0);
+  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, false>(tile, wf2, b2, y, g2, n, oy0, ox0);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,8 +903,22 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
     const FrameDesc f1 = frames[pd.f1], f2 = frames[pd.f2];
     const float* hp = half + p * (int64_t)h * w * 2;
     const uint8_t* a = f2.y;
-    const int32_t p2 = (int32_t)f2.pitch;
+    const uint32_t p2 = (uint32_t)f2.pitch;
     const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
+    // the first frame's 8 luma bytes in one load where the row is 8-byte aligned
+    uint8_t y1v[8];
+    if (((reinterpret_cast<uintptr_t>(f1.y) | (uintptr_t)f1.pitch) & 7u) == 0) {
+      typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+      const u32x2_t v8 = ldg32(reinterpret_cast<const u32x2_t*>(row1), (uint32_t)xb);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        y1v[k] = (uint8_t)(v8.x >> (8 * k));
+        y1v[4 + k] = (uint8_t)(v8.y >> (8 * k));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) y1v[k] = ldg32(row1, (uint32_t)(xb + k));
+    }
     // The 8 pixels read half-resolution columns k-1 .. k+4 (k = xb/2, clamped)
     // of two rows: 12 loads instead of 32.  Pixel j's taps (up_tap) are
     // columns (j+1)/2 and (j+1)/2 + 1 of that window; at the clamped image
@@ -912,8 +930,10 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const int32_t col = min(max(k0 + c, 0), w - 1);
-      r0[c] = *reinterpret_cast<const float2*>(hp + ((int64_t)ty.i0 * w + col) * 2);
-      r1[c] = *reinterpret_cast<const float2*>(hp + ((int64_t)ty.i1 * w + col) * 2);
+      const f32x2_t t0 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i0 * (uint32_t)w + (uint32_t)col));
+      const f32x2_t t1 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i1 * (uint32_t)w + (uint32_t)col));
+      r0[c] = make_float2(t0.x, t0.y);
+      r1[c] = make_float2(t1.x, t1.y);
     }
     float fu8[8], fv8[8];
 #pragma unroll
@@ -933,9 +953,10 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
       if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
       if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
       const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
-      const float top = (1.f - fx) * a[yi * p2 + xi] + fx * a[yi * p2 + x1];
-      const float bot = (1.f - fx) * a[y1 * p2 + xi] + fx * a[y1 * p2 + x1];
-      r += fabsf((1.f - fy) * top + fy * bot - (float)row1[x]);
+      const uint32_t o0 = (uint32_t)yi * p2, o1 = (uint32_t)y1 * p2;
+      const float top = (1.f - fx) * ldg32(a, o0 + (uint32_t)xi) + fx * ldg32(a, o0 + (uint32_t)x1);
+      const float bot = (1.f - fx) * ldg32(a, o1 + (uint32_t)xi) + fx * ldg32(a, o1 + (uint32_t)x1);
+      r += fabsf((1.f - fy) * top + fy * bot - (float)y1v[k]);
     }
     float* ou = pd.out + (int64_t)y * W + xb;
     float* ov = ou + (int64_t)W * H;

@@ -68,6 +68,24 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
   return (bf16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+// Global load at a base pointer plus a 32-bit byte offset (no per-lane
+// 64-bit address arithmetic; the access is known to be global memory).
+template <typename T>
+__device__ __forceinline__ T ldg32(const T* base, uint32_t byte_off) {
+  return *(const __attribute__((address_space(1))) T*)(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stg32(T* base, uint32_t byte_off, T v) {
+  *(__attribute__((address_space(1))) T*)(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// Two floats to packed BF16 (a in the low half), round to nearest even: one
+// v_cvt_pk_bf16_f32 on gfx950; equal to f2bf on finite inputs.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
 
 }  // namespace sg
 }  // namespace scn

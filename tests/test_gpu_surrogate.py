@@ -188,3 +188,50 @@ def test_gate_routing_and_residual():
     for k in range(3):
         ref = plain[k] if fb3[k] else net_only[k]
         assert torch.equal(mix[k], ref)
+
+
+def test_trained_network_gain():
+    """What training buys.  On held-out pairs of the training family (512x384
+    layered scenes, seeds 4,100,000+, 24 and 96 steps apart) the packaged trained
+    network's flow is much closer to the plain solver's than zero flow and
+    than the same network untrained; on held-out 1080p pairs (seed 23, rows
+    24 apart, as in the benchmark stream) the gated path stays within the
+    0.5 px mean-EPE budget."""
+    need_gpu()
+    import os
+    from paper_1805_07339_amd import train as T
+    if not os.path.exists(T.DEFAULT_WEIGHTS):
+        pytest.skip("no trained checkpoint")
+    master, meta = T.load(T.DEFAULT_WEIGHTS, "cuda")
+    net, net0 = scn.net_pack(master), scn.net_pack(T.he_init(1).cuda())
+
+    def epe(f, ref):
+        return float(torch.sqrt(((f - ref) ** 2).sum(dim=1)).mean())
+
+    W, H = 512, 384
+    frames = []
+    for i in range(8):
+        sc = synth.layered_scene(4_100_000 + i, W, H)
+        gap = 24 if i % 2 == 0 else 96
+        frames += [sc.nv12(100 + 7 * i, device="cuda").reshape(-1),
+                   sc.nv12(100 + 7 * i + gap, device="cuda").reshape(-1)]
+    tab = scn.Table.from_tensor(torch.stack(frames), W, H)
+    job = scn.Job(tab, scn.Sampling.range([(2 * i, 2 * i + 2) for i in range(8)]))
+    (plain,) = scn.flow([job], scn.flow_params(4, 10.0, 50))
+    (trained,) = scn.surrogate_infer([job], net)
+    (untrained,) = scn.surrogate_infer([job], net0)
+    e_trained, e_untrained, e_zero = epe(trained, plain), epe(untrained, plain), epe(torch.zeros_like(plain), plain)
+    print("512x384 held-out: mean EPE vs plain: trained %.3f, untrained %.3f, zero flow %.3f"
+          % (e_trained, e_untrained, e_zero))
+    assert e_trained < 0.5 * e_zero
+    assert e_trained < 0.5 * e_untrained
+
+    W, H, n = 1920, 1080, 7
+    scene = synth.layered_scene(23, W, H)
+    big = torch.stack([scene.nv12(24 * k, device="cuda").reshape(-1) for k in range(n)])
+    jb = scn.Job(scn.Table.from_tensor(big, W, H), scn.Sampling.stride(1, 0, n))
+    (plain_b,) = scn.flow([jb], scn.flow_params(4, 10.0, 50))
+    (gated,), (fb,), _ = scn.flow_surrogate([jb], net, float(meta["tau"]))
+    e_gated = epe(gated, plain_b)
+    print("1080p held-out: gated mean EPE %.3f (fallback %d/%d)" % (e_gated, int(fb.sum()), n - 1))
+    assert e_gated <= 0.5
