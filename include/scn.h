@@ -105,7 +105,8 @@ typedef struct {
  * with tile_variant = 0 runs one sweep per launch; otherwise sweeps_per_pass
  * sweeps (1..63) run per launch on register tiles of variant 1..4 (128 x 128,
  * 128 x 128, 128 x 64, 128 x 64 pixels), or on 128-column strips streamed
- * row by row with variants 5..7 (at most 6, 8, 10 sweeps per launch).  Every
+ * row by row with variants 5..8 (at most 6, 8, 10, 10 sweeps per launch;
+ * variant 8 streams bands of up to 1024 rows instead of 256).  Every
  * schedule gives bitwise identical results. */
 typedef struct {
   int32_t levels;

@@ -695,12 +695,14 @@ LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
 }  // namespace
 
 // Jacobi kernel variants: (rows per wave, waves per workgroup); variant 0 is
-// the one-sweep reference kernel.
+// the one-sweep reference kernel.  Streaming variants use rows = 0, waves =
+// the largest sweep count K, and cap their band height at band_cap rows
+// (taller bands re-read fewer halo rows but give fewer waves).
 struct JacobiVariant {
-  int32_t rows, waves;  // tile variants; streaming variants use rows = 0 and waves = K
+  int32_t rows, waves, band_cap;
 };
-constexpr JacobiVariant kVariants[] = {{1, 4}, {8, 16}, {16, 8}, {8, 8}, {4, 16}, {0, 6}, {0, 8}, {0, 10}};
-constexpr int kBandRows = 256;  // rows per streaming band
+constexpr JacobiVariant kVariants[] = {{1, 4, 0},    {8, 16, 0},   {16, 8, 0},    {8, 8, 0},  {4, 16, 0},
+                                       {0, 6, 256},  {0, 8, 256},  {0, 10, 256},  {0, 10, 1024}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct JacobiChoice {
@@ -750,7 +752,7 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     // chip (more bands only add waves when more pairs fall back).
     const int64_t n_eff = c.active ? std::max<int64_t>(1, (n_pairs + 7) / 8) : n_pairs;
     int64_t bh = (int64_t)g.h * strips * n_eff / want;
-    bh = std::max<int64_t>(64, std::min<int64_t>(kBandRows, bh));
+    bh = std::max<int64_t>(64, std::min<int64_t>(v.band_cap, bh));
     const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
     const int32_t band_h = (g.h + bands - 1) / bands;
     const int64_t units = (int64_t)strips * bands * n_pairs;

@@ -128,7 +128,7 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
     set_error("sweeps_per_pass must be in [0, 63]");
     return SCN_EINVAL;
   }
-  if (p->tile_variant < 0 || p->tile_variant > 7) { set_error("tile_variant must be in [0, 7]"); return SCN_EINVAL; }
+  if (p->tile_variant < 0 || p->tile_variant > 8) { set_error("tile_variant must be in [0, 8]"); return SCN_EINVAL; }
   if (t) {
     auto d = level_dims(t->width, t->height, p->levels);
     if (d.back().w < 2 || d.back().h < 2) {

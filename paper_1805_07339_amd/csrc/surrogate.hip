@@ -373,16 +373,19 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
 // reaches HBM (the unfused pair writes and re-reads it: 64 B per half-res
 // pixel).  conv1 uses the same fragments, MFMA and rounding as k_conv_fwd<0>,
 // so the conv2 input is bitwise the same.
-template <int TOH, int TOW, int NWAVE>
-__global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
-                                                       bf16_t* __restrict__ y, CGeom g1, CGeom g2, int32_t tiles_x,
-                                                       int32_t tiles_per_img) {
+template <int TOH, int TOW, int NWAVE, bool BLDS>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restrict__ frames,
+                                                       const PairDesc* __restrict__ pairs,
+                                                       const uint8_t* __restrict__ blob, bf16_t* __restrict__ y,
+                                                       CGeom g1, CGeom g2, int32_t tiles_x, int32_t tiles_per_img) {
   constexpr int IH = 2 * TOH + 1, IW = 2 * TOW + 1, CP = 32 + 8;  // conv2 input tile = conv1 outputs
   constexpr int XH = IH + 2, XW = IW + 2;                          // net-input tile
   constexpr int NT = 64 * NWAVE;
   static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].stride == 2, "layer shapes");
+  constexpr int W2 = BLDS ? 9 * 64 * 32 : 8;  // conv2's forward weights [tap][co][ci]
   __shared__ uint32_t xt[XH * XW];  // two bf16 channels per pixel
   __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
+  __shared__ __attribute__((aligned(16))) bf16_t wlds[W2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
   const int n = blockIdx.x / tiles_per_img;
@@ -391,15 +394,26 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict_
   const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
   const int xy0 = cy0 - 1, xx0 = cx0 - 1;          // net-input coordinates of xt (0, 0)
 
+  // The network input is formed here from the two frames' luma (the same
+  // arithmetic as k_net_input): per half-resolution pixel the 2x2 mean
+  // (round half up) as (v - 128) / 64 in BF16, channel 0 = first frame.
   constexpr int NX = XH * XW, ITX = (NX + NT - 1) / NT;
-  const uint32_t* x32 = reinterpret_cast<const uint32_t*>(x);
+  const PairDesc pd = pairs[n];
+  const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
+  const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
   uint32_t xr[ITX];
 #pragma unroll
   for (int i = 0; i < ITX; ++i) {
     const int e = min(tid + i * NT, NX - 1);
     const int yy = xy0 + e / XW, xx = xx0 + e % XW;
     const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
-    const uint32_t v = x32[((int64_t)n * g1.hi + (ok ? yy : 0)) * g1.wi + (ok ? xx : 0)];
+    const uint32_t ry = 2u * (uint32_t)(ok ? yy : 0), rx = 2u * (uint32_t)(ok ? xx : 0);
+    const int s1 = (int)ldg32(fa.y, ry * pa + rx) + ldg32(fa.y, ry * pa + rx + 1) + ldg32(fa.y, (ry + 1) * pa + rx) +
+                   ldg32(fa.y, (ry + 1) * pa + rx + 1);
+    const int s2 = (int)ldg32(fb.y, ry * pbp + rx) + ldg32(fb.y, ry * pbp + rx + 1) +
+                   ldg32(fb.y, (ry + 1) * pbp + rx) + ldg32(fb.y, (ry + 1) * pbp + rx + 1);
+    const uint32_t v = (uint32_t)f2bf((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f)) |
+                       ((uint32_t)f2bf((float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f)) << 16);
     xr[i] = ok ? v : 0u;
   }
   const bf16_t* wf1 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(0));
@@ -407,9 +421,17 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict_
   bf16x8 bw[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) bw[nb] = ld8(wf1 + (nb * 16 + r16) * 32 + kg * 8);
+  constexpr int NW8 = BLDS ? W2 / 8 : 0, WIT = (NW8 + NT - 1) / NT;
+  const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(1));
+  uint4 wreg[WIT > 0 ? WIT : 1];
+#pragma unroll
+  for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
 #pragma unroll
   for (int i = 0; i < ITX; ++i)
     if (tid + i * NT < NX) xt[tid + i * NT] = xr[i];
+#pragma unroll
+  for (int i = 0; i < WIT; ++i)
+    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
   __syncthreads();
 
   // per lane: the xt offsets of its four taps (lane group kg covers taps
@@ -456,9 +478,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const bf16_t* __restrict_
     }
   }
   __syncthreads();
-  const bf16_t* wf2 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
+  const bf16_t* wf2 = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
   const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
-  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, false>(tile, wf2, b2, y, g2, n, oy0, ox0);
+  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, BLDS>(tile, wf2, b2, y, g2, n, oy0, ox0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1184,25 +1206,29 @@ scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float
   return SCN_OK;
 }
 
-scn_status launch_conv12(const bf16_t* x, const uint8_t* blob, bf16_t* y, const NetDims& d, int64_t n,
-                          hipStream_t s) {
+scn_status launch_conv12(const FrameDesc* frames, const PairDesc* pairs, const uint8_t* blob, bf16_t* y,
+                          const NetDims& d, int64_t n, hipStream_t s) {
   constexpr int TOH = FwdTile<1>::TOH, TOW = FwdTile<1>::TOW, NW = FwdTile<1>::NWAVE;
+  constexpr bool BL = FwdTile<1>::BLDS;
   const CGeom g1 = layer_geom(d, 0, n), g2 = layer_geom(d, 1, n);
   const int32_t tx = (g2.wo + TOW - 1) / TOW, ty = (g2.ho + TOH - 1) / TOH;
   const int64_t grid = (int64_t)tx * ty * n;
   if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
   KernelTimer timer("conv_fwd", s);
   KernelTimer timer_l("conv_fwd12", s);
-  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y, g1, g2, tx,
+  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, frames, pairs, blob, y, g1,
+                     g2, tx,
                      tx * ty);
   SCN_LAUNCHED("fused conv1 + conv2 launch");
   return SCN_OK;
 }
 
-// Inference forward: conv1 and conv2 fused (conv1's activation is not kept).
-scn_status net_forward_infer(const NetDims& d, int64_t n, const uint8_t* blob, const NetBuffers& b, hipStream_t s) {
+// Inference forward: the network input, conv1 and conv2 in one kernel
+// (neither the input nor conv1's activation is kept).
+scn_status net_forward_infer(const FrameDesc* frames, const PairDesc* pairs, const NetDims& d, int64_t n,
+                             const uint8_t* blob, const NetBuffers& b, hipStream_t s) {
   scn_status st;
-  if ((st = launch_conv12(b.x, blob, b.act[1], d, n, s)) != SCN_OK) return st;
+  if ((st = launch_conv12(frames, pairs, blob, b.act[1], d, n, s)) != SCN_OK) return st;
   if ((st = launch_fwd<2>(b.act[1], blob, b.act[2], layer_geom(d, 2, n), s)) != SCN_OK) return st;
   if ((st = launch_fwd<3>(b.act[2], blob, b.act[3], layer_geom(d, 3, n), s)) != SCN_OK) return st;
   if ((st = launch_fwd<4>(b.act[3], blob, b.act[4], layer_geom(d, 4, n), s)) != SCN_OK) return st;
@@ -1435,8 +1461,7 @@ scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* 
   const sg::NetDims d = sg::net_dims(grp.w, grp.h);
   const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
   const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
-  if ((st = sg::launch_net_input(frames, pairs, b.x, d, ch.n_pairs, s)) != SCN_OK) return st;
-  if ((st = sg::net_forward_infer(d, ch.n_pairs, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+  if ((st = sg::net_forward_infer(frames, pairs, d, ch.n_pairs, (const uint8_t*)net, b, s)) != SCN_OK) return st;
   return sg::launch_flow_up(b.half, pairs, d, ch.n_pairs, s);
 }
 
@@ -1468,8 +1493,7 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
       uint8_t* factive = active + align_up((size_t)n);
       const FrameDesc* frames = (const FrameDesc*)(base + ch.frames_off);
       const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
-      if ((st = sg::launch_net_input(frames, pairs, b.x, d, n, s)) != SCN_OK) return st;
-      if ((st = sg::net_forward_infer(d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
+      if ((st = sg::net_forward_infer(frames, pairs, d, n, (const uint8_t*)net, b, s)) != SCN_OK) return st;
       if ((st = sg::launch_up_gate(b.half, frames, pairs, gpart, d, n, gate_tau, active, s)) != SCN_OK) return st;
       const int64_t fw = (ch.n_frames + 3) / 4;
       hipLaunchKernelGGL(sg::k_zero_bytes, dim3((unsigned)((fw + 255) / 256)), dim3(256), 0, s, (uint32_t*)factive,
