@@ -128,24 +128,29 @@ __global__ void __launch_bounds__(kThreads) k_hist16(FrameGeom g, const int64_t*
     const int32_t di = kThreads % g.nseg_x, dj = kThreads / g.nseg_x;
     int32_t s = s0 + tid;
     int32_t j = s / g.nseg_x, i = s % g.nseg_x;
-    uint4 a0, a1, a2;
-    if (s < s1) {
-      const uint8_t* yr = frame + (int64_t)(2 * j) * g.pitch + 16 * i;
-      a0 = *reinterpret_cast<const uint4*>(yr);
-      a1 = *reinterpret_cast<const uint4*>(yr + g.pitch);
-      a2 = *reinterpret_cast<const uint4*>(uvp + (int64_t)j * g.pitch + 16 * i);
-    }
-    for (; s < s1; s += kThreads) {
-      const uint4 c0 = a0, c1 = a1, c2 = a2;
+    // two segments in flight: (a*) is the next one to count, (b*) the one after
+    uint4 a0, a1, a2, b0, b1, b2;
+    auto load_seg = [&](int32_t jj, int32_t ii, uint4& y0, uint4& y1, uint4& uv) {
+      const uint8_t* yr = frame + (int64_t)(2 * jj) * g.pitch + 16 * ii;
+      y0 = *reinterpret_cast<const uint4*>(yr);
+      y1 = *reinterpret_cast<const uint4*>(yr + g.pitch);
+      uv = *reinterpret_cast<const uint4*>(uvp + (int64_t)jj * g.pitch + 16 * ii);
+    };
+    auto advance = [&]() {
       i += di;
       j += dj;
       if (i >= g.nseg_x) { i -= g.nseg_x; ++j; }
-      if (s + kThreads < s1) {  // prefetch the next segment before counting this one
-        const uint8_t* yr = frame + (int64_t)(2 * j) * g.pitch + 16 * i;
-        a0 = *reinterpret_cast<const uint4*>(yr);
-        a1 = *reinterpret_cast<const uint4*>(yr + g.pitch);
-        a2 = *reinterpret_cast<const uint4*>(uvp + (int64_t)j * g.pitch + 16 * i);
-      }
+    };
+    if (s < s1) load_seg(j, i, a0, a1, a2);
+    advance();
+    if (s + kThreads < s1) load_seg(j, i, b0, b1, b2);
+    for (; s < s1; s += kThreads) {
+      const uint4 c0 = a0, c1 = a1, c2 = a2;
+      a0 = b0;
+      a1 = b1;
+      a2 = b2;
+      advance();
+      if (s + 2 * kThreads < s1) load_seg(j, i, b0, b1, b2);  // two segments ahead
       count_seg16(lds, c0, c1, c2, lane4);
     }
   }
@@ -405,9 +410,10 @@ scn_status launch_hist(const scn_table& t, const int64_t* rows_dev, int64_t m, u
   const bool vec = vec_ok(t);
   g.nseg_x = vec ? t.width / 16 : 0;
   g.ntail_x = (t.width - 16 * g.nseg_x) / 2;
-  // about 8 segments (256 pixels) per thread per workgroup
+  // about 16 segments (512 pixels) per thread per workgroup (the per-workgroup
+  // clearing and folding of the LDS counters is then a small share)
   const int64_t px = (int64_t)t.width * t.height;
-  g.chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(4096, px / (kThreads * 256)));
+  g.chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(4096, px / (kThreads * 512)));
   const int64_t grid = m * g.chunks;
   if (grid > 0x7FFFFFFF) { set_error("too many frames for one HIST launch"); return SCN_EUNSUPPORTED; }
   KernelTimer timer("hist16", s);

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -363,6 +365,84 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
 
   const bf16_t* wf = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
   conv_tile_mma<L, TOH, TOW, NWAVE, SH, SW, BLDS>(tile, wf, bias, y, g, n, oy0, ox0);
+}
+
+// Persistent form of the LDS-tiled forward convolution for layers whose
+// weights live in LDS: a workgroup stages the weights once and then walks
+// output tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...  The input tile
+// is double-buffered: the global loads of the next tile are issued before
+// the MFMAs of the current one and written to the other LDS buffer after
+// them, so staging overlaps compute, and the weight tensor crosses the
+// memory hierarchy once per workgroup instead of once per tile.
+template <int L, int TOH, int TOW, int NWAVE>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_pers(const bf16_t* __restrict__ x,
+                                                              const uint8_t* __restrict__ blob, void* __restrict__ y,
+                                                              CGeom g, int32_t tiles_x, int32_t tiles_per_img,
+                                                              int32_t n_tiles) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO);
+  constexpr bool UP = D.up != 0;
+  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int NT = 64 * NWAVE;
+  constexpr int WELEMS = 9 * COP * CI;
+  static_assert(CI % 32 == 0 && TOW % 16 == 0 && (TOH * TOW / 16) % NWAVE == 0, "tile shape");
+  static_assert(!UP || (S == 1 && TOH % 2 == 0 && TOW % 2 == 0), "upsampled tile shape");
+  constexpr int SH = UP ? IH / 2 + 1 : IH, SW = UP ? IW / 2 + 1 : IW;
+  constexpr int TILE = SH * SW * CP;
+  __shared__ __attribute__((aligned(16))) bf16_t tile[2 * TILE];
+  __shared__ __attribute__((aligned(16))) bf16_t wlds[WELEMS];
+  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
+  const int tid = threadIdx.x;
+  constexpr int NW8 = WELEMS / 8, WIT = (NW8 + NT - 1) / NT;
+  constexpr int NE = SH * SW * (CI / 8), IT = (NE + NT - 1) / NT;
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  uint4 treg[IT];
+  // global loads of tile t's input into treg (zero outside the image)
+  auto load_tile = [&](int t) {
+    const int n = t / tiles_per_img, r = t % tiles_per_img;
+    const int iy0 = (r / tiles_x) * TOH * S - 1, ix0 = (r % tiles_x) * TOW * S - 1;
+    const bf16_t* ximg = x + (int64_t)n * g.hi * g.wi * CI;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = min(tid + i * NT, NE - 1);
+      const int ch = e % (CI / 8), p = e / (CI / 8);
+      const int yy = (UP ? (iy0 >> 1) : iy0) + p / SW, xx = (UP ? (ix0 >> 1) : ix0) + p % SW;
+      const bool ok = yy >= 0 && yy < g.hi && xx >= 0 && xx < g.wi;
+      const int sy = ok ? yy : 0, sx = ok ? xx : 0;
+      const u32x4_t v = ldg32(reinterpret_cast<const u32x4_t*>(ximg), 2u * (uint32_t)((sy * g.wi + sx) * CI + ch * 8));
+      treg[i] = ok ? make_uint4(v.x, v.y, v.z, v.w) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto store_tile = [&](bf16_t* buf) {
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NT;
+      if (e < NE) *reinterpret_cast<uint4*>(buf + (e / (CI / 8)) * CP + (e % (CI / 8)) * 8) = treg[i];
+    }
+  };
+  int t = blockIdx.x;
+  if (t >= n_tiles) return;  // uniform over the workgroup, before any barrier
+  {
+    const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
+    uint4 wreg[WIT];
+#pragma unroll
+    for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
+    load_tile(t);
+#pragma unroll
+    for (int i = 0; i < WIT; ++i)
+      if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+    store_tile(tile);
+  }
+  __syncthreads();
+  for (int buf = 0; t < n_tiles; t += gridDim.x, buf ^= 1) {
+    const int tn = t + gridDim.x;
+    if (tn < n_tiles) load_tile(tn);  // in flight during this tile's MFMAs
+    const int n = t / tiles_per_img, r = t % tiles_per_img;
+    conv_tile_mma<L, TOH, TOW, NWAVE, SH, SW, true>(tile + buf * TILE, wlds, bias, y, g, n, (r / tiles_x) * TOH,
+                                                    (r % tiles_x) * TOW);
+    if (tn < n_tiles) store_tile(tile + (buf ^ 1) * TILE);  // that buffer was last read before the previous barrier
+    __syncthreads();
+  }
 }
 
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
@@ -957,11 +1037,17 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
       r0[c] = make_float2(t0.x, t0.y);
       r1[c] = make_float2(t1.x, t1.y);
     }
+    // Away from the left and right image borders the horizontal taps are
+    // fixed: weights 0.75 / 0.25 for even / odd pixels (exact values of
+    // up_tap there), so the per-pixel tap arithmetic is skipped.
+    const bool interior = xb > 0 && xb + 8 < W;
     float fu8[8], fv8[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int32_t x = xb + k;
-      const UpTap tx = up_tap(x, w);
+      UpTap tx;
+      if (interior) tx.f = (k & 1) ? 0.25f : 0.75f;
+      else tx = up_tap(x, w);
       constexpr int kIa[8] = {0, 1, 1, 2, 2, 3, 3, 4};
       const float2 fa = r0[kIa[k]], fb = r0[kIa[k] + 1], fc = r1[kIa[k]], fd = r1[kIa[k] + 1];
       const float uu = (1.f - ty.f) * ((1.f - tx.f) * fa.x + tx.f * fb.x) + ty.f * ((1.f - tx.f) * fc.x + tx.f * fd.x);
@@ -1145,9 +1231,13 @@ constexpr int kMR = 2;  // 16-pixel row blocks per wave
 // output tile with 8 waves, conv4 8 x 32 with 8 waves (two pixel blocks per
 // wave keep it at two waves per SIMD), conv3 4 x 16 with 2 waves (its
 // stride-2 input tile would otherwise hold the CU's LDS alone), the others
-// 8 x 32 (4 x 32 for stride 2) with 4 waves.
+// 8 x 32 (4 x 32 for stride 2) with 4 waves.  conv4 and conv5 run
+// persistent (one workgroup per resident slot, weights staged once, next
+// input tile loaded while the current one is multiplied); conv6, whose
+// weights are small, is faster with one workgroup per tile.
 template <int L> struct FwdTile {
   static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
+  static constexpr bool PERS = (L == 3 || L == 4);
   static constexpr int TOH = kNet[L].stride == 2 ? 4 : (L == 5 ? 16 : 8), TOW = L == 2 ? 16 : 32;
   static constexpr int NWAVE = (L == 5 || L == 3) ? 8 : (L == 2 ? 2 : 4);
 };
@@ -1170,8 +1260,38 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
     const int32_t tx = (g.wo + TOW - 1) / TOW, ty = (g.ho + TOH - 1) / TOH;
     const int64_t grid = (int64_t)tx * ty * g.n;
     if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
-    hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y,
-                       g, tx, tx * ty);
+    if constexpr (FwdTile<L>::PERS) {
+      // persistent: as many workgroups as the device holds at once (queried
+      // once per device)
+      static std::map<int, int> resident_by_dev;
+      static std::mutex mu;
+      int resident = 0;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) { set_error("HIP device query failed"); return SCN_EHIP; }
+        resident = resident_by_dev[dev];
+      }
+      if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_fwd_pers<L, TOH, TOW, NW>, 64 * NW, 0) !=
+                hipSuccess) {
+          set_error("HIP device query failed");
+          return SCN_EHIP;
+        }
+        resident = std::max(1, cus * std::max(1, per_cu));
+        std::lock_guard<std::mutex> lk(mu);
+        resident_by_dev[dev] = resident;
+      }
+      const int64_t wgs = std::min<int64_t>(grid, resident);
+      hipLaunchKernelGGL((k_conv_fwd_pers<L, TOH, TOW, NW>), dim3((unsigned)wgs), dim3(64 * NW), 0, s, x, blob, y, g,
+                         tx, tx * ty, (int32_t)grid);
+    } else {
+      hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y,
+                         g, tx, tx * ty);
+    }
   }
   SCN_LAUNCHED("conv forward launch");
   return SCN_OK;
