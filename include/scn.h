@@ -64,8 +64,10 @@ typedef enum {
  * Row f starts at frames + f * frame_bytes and holds the Y plane (height rows
  * of pitch bytes, the first width bytes used) followed by the interleaved
  * chroma plane (height/2 rows of pitch bytes: U0 V0 U1 V1 ...).
- * width and height are even and >= 2; pitch >= width;
- * frame_bytes >= pitch * height * 3 / 2.
+ * width and height are even and >= 2 and at most 32768; width <= pitch <=
+ * 2^20; frame_bytes >= pitch * height * 3 / 2, and that Y + UV extent is at
+ * most 2 GiB (kernels address a frame with 32-bit offsets).  Tables outside
+ * these limits are refused with SCN_EUNSUPPORTED.
  * Only the rows a call samples are read, so only those rows need to be backed
  * by memory (a table may be a view of which a window of rows is resident). */
 typedef struct {
@@ -105,8 +107,9 @@ typedef struct {
  * with tile_variant = 0 runs one sweep per launch; otherwise sweeps_per_pass
  * sweeps (1..63) run per launch on register tiles of variant 1..4 (128 x 128,
  * 128 x 128, 128 x 64, 128 x 64 pixels), or on 128-column strips streamed
- * row by row with variants 5..8 (at most 6, 8, 10, 10 sweeps per launch;
- * variant 8 streams bands of up to 1024 rows instead of 256).  Every
+ * row by row with variants 5..10 (at most 6, 8, 10, 10, 10, 10 sweeps per
+ * launch; variants 8 and 10 stream bands of up to 1024 rows instead of 256;
+ * variants 9 and 10 keep six input rows in flight instead of three).  Every
  * schedule gives bitwise identical results. */
 typedef struct {
   int32_t levels;

@@ -72,13 +72,18 @@ __device__ __forceinline__ T* as_global(T* p) {
 }
 // Load of a global element at a (wave-uniform) base plus a 32-bit byte
 // offset: a scalar base and one VGPR offset, no per-lane 64-bit arithmetic.
+// The base is converted to a global pointer before the offset is added, so
+// that the sum is a global-address-space sum (scalar base + 32-bit vector
+// offset in one instruction) rather than a 64-bit generic sum per lane.
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) const char gcchar;
 template <typename T>
 __device__ __forceinline__ T ldg(const T* base, uint32_t byte_off) {
-  return *(const __attribute__((address_space(1))) T*)(reinterpret_cast<const char*>(base) + byte_off);
+  return *(const __attribute__((address_space(1))) T*)((gcchar*)base + byte_off);
 }
 template <typename T>
 __device__ __forceinline__ void stg(T* base, uint32_t byte_off, T v) {
-  *(__attribute__((address_space(1))) T*)(reinterpret_cast<char*>(base) + byte_off) = v;
+  *(__attribute__((address_space(1))) T*)((gchar*)base + byte_off) = v;
 }
 
 // (u, v) buffer codes: 0 and 1 are the pair's ping-pong buffers, 2 is the output.
@@ -133,19 +138,6 @@ __device__ __forceinline__ float bilinear_split(F at, int32_t w, int32_t h, int3
   return (1.f - fy) * top + fy * bot;
 }
 
-// Start flow of a pixel: 2 * bilinear(coarse, x/2, y/2), or 0 at the coarsest level.
-__device__ __forceinline__ void start_flow(const float* cu, const float* cv, const LevelGeom& g, int32_t x, int32_t y,
-                                           float* u0, float* v0) {
-  if (!g.has_coarse) { *u0 = 0.f; *v0 = 0.f; return; }
-  const int32_t xi = x >> 1, yi = y >> 1;
-  const float xf = (x & 1) ? 0.5f : 0.f, yf = (y & 1) ? 0.5f : 0.f;
-  const uint32_t cw4 = 4u * (uint32_t)g.cw;
-  auto atu = [&](int32_t xx, int32_t yy) { return ldg(cu, (uint32_t)yy * cw4 + 4u * (uint32_t)xx); };
-  auto atv = [&](int32_t xx, int32_t yy) { return ldg(cv, (uint32_t)yy * cw4 + 4u * (uint32_t)xx); };
-  *u0 = 2.f * bilinear_split(atu, g.cw, g.ch, xi, xf, yi, yf);
-  *v0 = 2.f * bilinear_split(atv, g.cw, g.ch, xi, xf, yi, yf);
-}
-
 // ---------------------------------------------------------------------------
 // pyramid: level l = even samples of blur5(level l-1), [1,4,6,4,1]/16
 // horizontal then vertical, clamp-to-edge.  A workgroup owns 16 x 64 output
@@ -160,9 +152,10 @@ __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, Le
   using T = typename std::conditional<U8, int, float>::type;
   __shared__ T sIn[kPyrIH][kPyrIW + 1];
   __shared__ T sH[kPyrIH][kPyrTW];
-  const int64_t f = blockIdx.x / tiles_per_frame;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t f = blk / tiles_per_frame;
   if (c.factive && !c.factive[f]) return;
-  const int32_t t = blockIdx.x % tiles_per_frame;
+  const int32_t t = blk % tiles_per_frame;
   const int32_t ox = (t % tiles_x) * kPyrTW, oy = (t / tiles_x) * kPyrTH;
   const int32_t ix0 = 2 * ox - 2, iy0 = 2 * oy - 2;
   const Img im = level_img(c, (int32_t)f, src);
@@ -239,9 +232,10 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   __shared__ float sI[kSetupTH + 2][kSetupTW + 2];
   __shared__ float sU[kSetupTH][kSetupTW];
   __shared__ float sV[kSetupTH][kSetupTW];
-  const int64_t pr = blockIdx.x / tiles_per_pair;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t pr = blk / tiles_per_pair;
   if (c.active && !c.active[pr]) return;
-  const int32_t t = blockIdx.x % tiles_per_pair;
+  const int32_t t = blk % tiles_per_pair;
   const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
   const PairDesc pd = c.pairs[pr];
   const uint8_t* y1 = nullptr;
@@ -262,16 +256,58 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   }
   // 32-bit byte offsets (a frame or pyramid level is far below 4 GiB)
   const uint32_t q1 = (uint32_t)p1, q2 = (uint32_t)p2;
+  // rows < 2^15 and pitches <= 2^20 (checked on the host): 24-bit products
   auto at1 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)ldg(y1, (uint32_t)yy * q1 + (uint32_t)xx);
-    else return ldg(f1, 4u * ((uint32_t)yy * q1 + (uint32_t)xx));
+    if constexpr (U8) return (float)ldg(y1, __umul24((uint32_t)yy, q1) + (uint32_t)xx);
+    else return ldg(f1, 4u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
   };
   auto at2 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)ldg(y2, (uint32_t)yy * q2 + (uint32_t)xx);
-    else return ldg(f2, 4u * ((uint32_t)yy * q2 + (uint32_t)xx));
+    if constexpr (U8) return (float)ldg(y2, __umul24((uint32_t)yy, q2) + (uint32_t)xx);
+    else return ldg(f2, 4u * (__umul24((uint32_t)yy, q2) + (uint32_t)xx));
   };
-  const float* cu = COARSE ? uv_buf(c, pr, coarse_code, g.n0) : nullptr;
-  const float* cv = COARSE ? cu + (int64_t)g.cw * g.ch : nullptr;
+  // Start flow = 2 * bilinear(coarse flow, x/2, y/2), separably: the
+  // horizontal interpolation of the coarse rows under the tile ((oy-1)/2 ..
+  // (oy+16)/2 + 1, at most 11, clamped to the coarse level) at each of the
+  // tile's 66 halo columns goes to LDS once; each halo pixel then combines
+  // two of those rows.  Same operands and operation order as the plain
+  // bilinear formula, so the values are identical.
+  constexpr int CH = kSetupTH / 2 + 3;
+  __shared__ float sHU[COARSE ? CH : 1][COARSE ? TW : 1];
+  __shared__ float sHV[COARSE ? CH : 1][COARSE ? TW : 1];
+  int32_t cy_lo = 0;
+  if constexpr (COARSE) {
+    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
+    const float* cv = cu + (int64_t)g.cw * g.ch;
+    cy_lo = min(max(oy - 1, 0) >> 1, g.ch - 1);
+    constexpr int NH = CH * TW, ITH = (NH + 255) / 256;
+    const uint32_t cw4 = 4u * (uint32_t)g.cw;
+    float ha[ITH], hb[ITH], hc[ITH], hd[ITH], hf[ITH];
+#pragma unroll
+    for (int i = 0; i < ITH; ++i) {
+      const int e = min((int)threadIdx.x + i * 256, NH - 1);
+      const int32_t yy = min(cy_lo + e / TW, g.ch - 1);
+      const int32_t x = clampi(ox + e % TW - 1, 0, g.w - 1), xi = x >> 1;
+      int32_t x0;
+      if (xi >= g.cw - 1) { x0 = g.cw - 1; hf[i] = 0.f; }
+      else { x0 = xi; hf[i] = (x & 1) ? 0.5f : 0.f; }
+      const int32_t x1 = min(x0 + 1, g.cw - 1);
+      const uint32_t r = __umul24((uint32_t)yy, cw4);
+      ha[i] = ldg(cu, r + 4u * (uint32_t)x0);
+      hb[i] = ldg(cu, r + 4u * (uint32_t)x1);
+      hc[i] = ldg(cv, r + 4u * (uint32_t)x0);
+      hd[i] = ldg(cv, r + 4u * (uint32_t)x1);
+    }
+#pragma unroll
+    for (int i = 0; i < ITH; ++i) {
+      const int e = threadIdx.x + i * 256;
+      if (e < NH) {
+        const float fx = hf[i];
+        sHU[e / TW][e % TW] = (1.f - fx) * ha[i] + fx * hb[i];
+        sHV[e / TW][e % TW] = (1.f - fx) * hc[i] + fx * hd[i];
+      }
+    }
+    __syncthreads();
+  }
   float rT[IT], rI[IT], rU[IT], rV[IT];
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
@@ -279,7 +315,16 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const int ty = e / TW, tx = e % TW;
     const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
     float u0 = 0.f, v0 = 0.f;
-    if constexpr (COARSE) start_flow(cu, cv, g, x, y, &u0, &v0);
+    if constexpr (COARSE) {
+      const int32_t yi = y >> 1;
+      int32_t y0;
+      float fy;
+      if (yi >= g.ch - 1) { y0 = g.ch - 1; fy = 0.f; }
+      else { y0 = yi; fy = (y & 1) ? 0.5f : 0.f; }
+      const int r0 = y0 - cy_lo, r1 = min(y0 + 1, g.ch - 1) - cy_lo;
+      u0 = 2.f * ((1.f - fy) * sHU[r0][tx] + fy * sHU[r1][tx]);
+      v0 = 2.f * ((1.f - fy) * sHV[r0][tx] + fy * sHV[r1][tx]);
+    }
     const float fu = floorf(u0), fv = floorf(v0);
     rT[i] = bilinear_split(at2, g.w, g.h, x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
     rI[i] = at1(x, y);
@@ -325,7 +370,7 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const float Itp = It - Ix * u0 - Iy * v0;
     const float den = alpha2 + Ix * Ix + Iy * Iy;
     const float r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
-    const uint32_t p4 = 4u * ((uint32_t)y * (uint32_t)g.w + (uint32_t)x);
+    const uint32_t p4 = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
     stg(pa, p4, Ix * r);
     stg(pb, p4, Iy * r);
     stg(pc, p4, Itp * r);
@@ -517,10 +562,12 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const float gcfloat;
 __device__ __forceinline__ gcfloat& at_off(const float* base, uint32_t byte_off) {
-  return *(gcfloat*)(reinterpret_cast<const char*>(base) + byte_off);
+  asm("" : "+v"(byte_off));
+  return *(gcfloat*)((gcchar*)base + byte_off);
 }
 __device__ __forceinline__ gfloat& at_off(float* base, uint32_t byte_off) {
-  return *(gfloat*)(reinterpret_cast<char*>(base) + byte_off);
+  asm("" : "+v"(byte_off));
+  return *(gfloat*)((gchar*)base + byte_off);
 }
 
 template <int K>
@@ -557,6 +604,9 @@ struct StStep {
       jac_update(ub1, vb1, ca.y, cb.y, cc.y, &N.y, &N.w);
       if constexpr (S < K) win[S][(U - S + 3 * K) % 3] = N;
       if constexpr (S == K) {
+        // keep the last sweep's arithmetic ahead of the lane-masked stores
+        // (sunk into them, its wave shifts could not fold into the adds)
+        asm volatile("" ::"v"(N.x), "v"(N.y), "v"(N.z), "v"(N.w));
         const int32_t r = ii - S;
         if (r >= y0 && r < y1) {
           float* ru = du + (int64_t)r * w;
@@ -576,24 +626,25 @@ struct StStep {
     }
   }
 
-  // Input row ii sits in prefetch slot U; once it has entered the window and
-  // the ring, the slot is refilled with row ii + 3 (three rows of loads in
-  // flight per wave).
-  template <int U, typename F>
-  __device__ __forceinline__ void step(int32_t ii, float4 (&nuv)[3], float2 (&na)[3], float2 (&nb)[3],
-                                       float2 (&nc)[3], F&& load_row) {
-    constexpr int RING = K + 1;
-    win[0][U] = nuv[U];
+  // Input row ii sits in prefetch slot U of P (P a multiple of 3, so that
+  // ii mod 3 = U mod 3 selects the window slot); once it has entered the
+  // window and the ring, the slot is refilled with row ii + P (P rows of
+  // loads in flight per wave).
+  template <int U, int P, typename F>
+  __device__ __forceinline__ void step(int32_t ii, float4 (&nuv)[P], float2 (&na)[P], float2 (&nb)[P],
+                                       float2 (&nc)[P], F&& load_row) {
+    constexpr int RING = K + 1, W = U % 3;
+    win[0][W] = nuv[U];
     const int rs = ((ii % RING) + RING) % RING;
     ring[rs][0][lane] = na[U];
     ring[rs][1][lane] = nb[U];
     ring[rs][2][lane] = nc[U];
-    load_row(ii + 3, nuv[U], na[U], nb[U], nc[U]);
-    sweep<U, 1>(ii);
+    load_row(ii + P, nuv[U], na[U], nb[U], nc[U]);
+    sweep<W, 1>(ii);
   }
 };
 
-template <int K>
+template <int K, int P>
 __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
                                                       int32_t strips, int32_t bands, int32_t band_h) {
   constexpr int RING = K + 1;
@@ -602,7 +653,7 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   // wave-uniform from here on: the pair, band, strip, row counters and plane
   // pointers live in SGPRs and their arithmetic runs on the scalar unit
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t unit = (int64_t)blockIdx.x * 4 + wv;          // (pair, band, strip)
+  const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wv;  // (pair, band, strip)
   const int64_t per_pair = (int64_t)strips * bands;
   const int64_t pr = unit / per_pair;
   if (pr >= c.n_pairs) return;
@@ -667,15 +718,21 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
       cc = make_float2(at_off(rc, bo0), at_off(rc, bo1));
     }
   };
-  float4 nuv[3];
-  float2 na[3], nb[3], nc[3];
+  float4 nuv[P];
+  float2 na[P], nb[P], nc[P];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
+  for (int q = 0; q < P; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
   StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1};
-  for (; i <= i_end; i += 3) {
-    st.template step<0>(i, nuv, na, nb, nc, load_row);
-    st.template step<1>(i + 1, nuv, na, nb, nc, load_row);
-    st.template step<2>(i + 2, nuv, na, nb, nc, load_row);
+  static_assert(P == 3 || P == 6, "prefetch depth");
+  for (; i <= i_end; i += P) {
+    st.template step<0, P>(i, nuv, na, nb, nc, load_row);
+    st.template step<1, P>(i + 1, nuv, na, nb, nc, load_row);
+    st.template step<2, P>(i + 2, nuv, na, nb, nc, load_row);
+    if constexpr (P == 6) {
+      st.template step<3, P>(i + 3, nuv, na, nb, nc, load_row);
+      st.template step<4, P>(i + 4, nuv, na, nb, nc, load_row);
+      st.template step<5, P>(i + 5, nuv, na, nb, nc, load_row);
+    }
   }
 }
 
@@ -696,13 +753,15 @@ LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
 
 // Jacobi kernel variants: (rows per wave, waves per workgroup); variant 0 is
 // the one-sweep reference kernel.  Streaming variants use rows = 0, waves =
-// the largest sweep count K, and cap their band height at band_cap rows
-// (taller bands re-read fewer halo rows but give fewer waves).
+// the largest sweep count K, cap their band height at band_cap rows (taller
+// bands re-read fewer halo rows but give fewer waves) and keep `prefetch`
+// input rows in flight per wave (3 or, for K = 10 passes, 6).
 struct JacobiVariant {
-  int32_t rows, waves, band_cap;
+  int32_t rows, waves, band_cap, prefetch;
 };
-constexpr JacobiVariant kVariants[] = {{1, 4, 0},    {8, 16, 0},   {16, 8, 0},    {8, 8, 0},  {4, 16, 0},
-                                       {0, 6, 256},  {0, 8, 256},  {0, 10, 256},  {0, 10, 1024}};
+constexpr JacobiVariant kVariants[] = {{1, 4, 0, 0},     {8, 16, 0, 0},    {16, 8, 0, 0},    {8, 8, 0, 0},
+                                       {4, 16, 0, 0},    {0, 6, 256, 3},   {0, 8, 256, 3},   {0, 10, 256, 3},
+                                       {0, 10, 1024, 3}, {0, 10, 256, 6},  {0, 10, 1024, 6}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct JacobiChoice {
@@ -759,12 +818,16 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     const int64_t grid = (units + 3) / 4;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     const dim3 gd((unsigned)grid), bd(256);
-    switch (K) {
+    if (K == 10 && v.prefetch == 6) {
+      hipLaunchKernelGGL((k_hs_jacobi_st<10, 6>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+    } else {
+      switch (K) {
 #define SCN_ST(k) \
-  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
-      SCN_ST(1) SCN_ST(2) SCN_ST(3) SCN_ST(4) SCN_ST(5) SCN_ST(6) SCN_ST(7) SCN_ST(8) SCN_ST(9) SCN_ST(10)
+  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k, 3>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
+        SCN_ST(1) SCN_ST(2) SCN_ST(3) SCN_ST(4) SCN_ST(5) SCN_ST(6) SCN_ST(7) SCN_ST(8) SCN_ST(9) SCN_ST(10)
 #undef SCN_ST
-      default: set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL;
+        default: set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL;
+      }
     }
     SCN_LAUNCHED("jacobi launch");
     return SCN_OK;

@@ -28,6 +28,11 @@ scn_status check_table(const scn_table* t) {
     set_error("frame dimensions above 32768 are not supported");
     return SCN_EUNSUPPORTED;
   }
+  // kernels address a frame with 32-bit byte offsets and 24-bit row products
+  if (t->pitch > (1 << 20) || need > ((int64_t)1 << 31)) {
+    set_error("table pitch above 2^20 bytes or frames above 2 GiB are not supported");
+    return SCN_EUNSUPPORTED;
+  }
   return SCN_OK;
 }
 
@@ -128,7 +133,7 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
     set_error("sweeps_per_pass must be in [0, 63]");
     return SCN_EINVAL;
   }
-  if (p->tile_variant < 0 || p->tile_variant > 8) { set_error("tile_variant must be in [0, 8]"); return SCN_EINVAL; }
+  if (p->tile_variant < 0 || p->tile_variant > 10) { set_error("tile_variant must be in [0, 10]"); return SCN_EINVAL; }
   if (t) {
     auto d = level_dims(t->width, t->height, p->levels);
     if (d.back().w < 2 || d.back().h < 2) {

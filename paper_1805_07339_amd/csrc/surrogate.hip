@@ -327,8 +327,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
   const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const int n = blockIdx.x / tiles_per_img;
-  const int t = blockIdx.x % tiles_per_img;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int n = blk / tiles_per_img;
+  const int t = blk % tiles_per_img;
   const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
   const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;
 
@@ -369,8 +370,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
 
 // Persistent form of the LDS-tiled forward convolution for layers whose
 // weights live in LDS: a workgroup stages the weights once and then walks
-// output tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...  The input tile
-// is double-buffered: the global loads of the next tile are issued before
+// output tiles t, t + gridDim.x, ...  The input tile is double-buffered: the global loads of the next tile are issued before
 // the MFMAs of the current one and written to the other LDS buffer after
 // them, so staging overlaps compute, and the weight tensor crosses the
 // memory hierarchy once per workgroup instead of once per tile.
@@ -420,7 +420,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_pers(const bf16_t* __re
       if (e < NE) *reinterpret_cast<uint4*>(buf + (e / (CI / 8)) * CP + (e % (CI / 8)) * 8) = treg[i];
     }
   };
-  int t = blockIdx.x;
+  // round k covers tiles k*G .. k*G + G - 1 (G = gridDim.x), spread so that
+  // each XCD takes a contiguous part of them
+  int t = xcd_block(blockIdx.x, gridDim.x);
   if (t >= n_tiles) return;  // uniform over the workgroup, before any barrier
   {
     const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
@@ -468,8 +470,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
   __shared__ __attribute__((aligned(16))) bf16_t wlds[W2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const int n = blockIdx.x / tiles_per_img;
-  const int t = blockIdx.x % tiles_per_img;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int n = blk / tiles_per_img;
+  const int t = blk % tiles_per_img;
   const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
   const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
   const int xy0 = cy0 - 1, xx0 = cx0 - 1;          // net-input coordinates of xt (0, 0)
@@ -996,8 +999,9 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
   // each thread: 8 consecutive pixels of one row (W is a multiple of 8)
   __shared__ float red[4];
   const int32_t W = 2 * w, H = 2 * h;
-  const int64_t p = blockIdx.x / blocks_per_pair;
-  const int32_t q = (blockIdx.x % blocks_per_pair) * 256 + threadIdx.x;  // 8-pixel group
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t p = blk / blocks_per_pair;
+  const int32_t q = (blk % blocks_per_pair) * 256 + threadIdx.x;  // 8-pixel group
   float r = 0.f;
   if (q < (W / 8) * H) {
     const int32_t y = q / (W / 8), xb = (q % (W / 8)) * 8;
@@ -1077,7 +1081,7 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
   for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) part[blk] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // One workgroup per pair: fixed-order strided sums, then a fixed tree, so the

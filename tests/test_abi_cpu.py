@@ -64,6 +64,13 @@ def test_odd_size_unsupported_and_bad_table_invalid():
     t2 = _cpu_table(4, 64, 48)
     t2.frame_bytes = 10
     assert scn.lib().scn_count_rows(ctypes.byref(scn.Job(t2, scn.Sampling.stride(1, 0, 4)).cjob)) == scn.SCN_EINVAL
+    # frames are addressed with 32-bit offsets: pitch above 2^20 is refused
+    # (validation only; the descriptor is never dereferenced)
+    t3 = _cpu_table(4, 64, 48)
+    t3.pitch = (1 << 20) + 64
+    t3.frame_bytes = t3.pitch * 72
+    assert scn.lib().scn_count_rows(ctypes.byref(scn.Job(t3, scn.Sampling.stride(1, 0, 4)).cjob)) == scn.SCN_EUNSUPPORTED
+    assert "pitch" in scn.lib().scn_last_error().decode()
 
 
 def test_hist_validation_before_any_device_work():
