@@ -642,6 +642,13 @@ struct StStep {
     load_row(ii + P, nuv[U], na[U], nb[U], nc[U]);
     sweep<W, 1>(ii);
   }
+  // steps U .. P-1 of one loop iteration (rows i + U ..)
+  template <int U, int P, typename F>
+  __device__ __forceinline__ void steps(int32_t i, float4 (&nuv)[P], float2 (&na)[P], float2 (&nb)[P],
+                                        float2 (&nc)[P], F&& load_row) {
+    step<U, P>(i + U, nuv, na, nb, nc, load_row);
+    if constexpr (U + 1 < P) steps<U + 1, P>(i, nuv, na, nb, nc, load_row);
+  }
 };
 
 template <int K, int P>
@@ -723,17 +730,8 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
 #pragma unroll
   for (int q = 0; q < P; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
   StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1};
-  static_assert(P == 3 || P == 6, "prefetch depth");
-  for (; i <= i_end; i += P) {
-    st.template step<0, P>(i, nuv, na, nb, nc, load_row);
-    st.template step<1, P>(i + 1, nuv, na, nb, nc, load_row);
-    st.template step<2, P>(i + 2, nuv, na, nb, nc, load_row);
-    if constexpr (P == 6) {
-      st.template step<3, P>(i + 3, nuv, na, nb, nc, load_row);
-      st.template step<4, P>(i + 4, nuv, na, nb, nc, load_row);
-      st.template step<5, P>(i + 5, nuv, na, nb, nc, load_row);
-    }
-  }
+  static_assert(P % 3 == 0, "prefetch depth must be a multiple of the 3 window slots");
+  for (; i <= i_end; i += P) st.template steps<0, P>(i, nuv, na, nb, nc, load_row);
 }
 
 LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
@@ -755,7 +753,8 @@ LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
 // the one-sweep reference kernel.  Streaming variants use rows = 0, waves =
 // the largest sweep count K, cap their band height at band_cap rows (taller
 // bands re-read fewer halo rows but give fewer waves) and keep `prefetch`
-// input rows in flight per wave (3 or, for K = 10 passes, 6).
+// input rows in flight per wave (3 or, for K = 10 passes, 6; 9 was measured
+// no faster than 6).
 struct JacobiVariant {
   int32_t rows, waves, band_cap, prefetch;
 };
@@ -765,8 +764,9 @@ constexpr JacobiVariant kVariants[] = {{1, 4, 0, 0},     {8, 16, 0, 0},    {16, 
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct JacobiChoice {
-  int32_t variant;  // index into kVariants
-  int32_t k;        // sweeps per pass (= halo)
+  int32_t variant;    // index into kVariants
+  int32_t k;          // sweeps per pass (= halo)
+  int32_t bands = 0;  // streaming variants: row bands per pair (0: sized from the pair count)
 };
 
 bool variant_fits(int v, int32_t k, const LevelGeom& g) {
@@ -812,6 +812,8 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     const int64_t n_eff = c.active ? std::max<int64_t>(1, (n_pairs + 7) / 8) : n_pairs;
     int64_t bh = (int64_t)g.h * strips * n_eff / want;
     bh = std::max<int64_t>(64, std::min<int64_t>(v.band_cap, bh));
+    // a tuned band count (the tail of the last round of waves depends on it)
+    if (jc.bands > 0) bh = (g.h + std::min(jc.bands, g.h) - 1) / std::min(jc.bands, g.h);
     const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
     const int32_t band_h = (g.h + bands - 1) / bands;
     const int64_t units = (int64_t)strips * bands * n_pairs;

@@ -1065,7 +1065,8 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
       if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
       if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
       const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
-      const uint32_t o0 = (uint32_t)yi * p2, o1 = (uint32_t)y1 * p2;
+      // rows < 2^15, pitch <= 2^20 (checked on the host): 24-bit products
+      const uint32_t o0 = __umul24((uint32_t)yi, p2), o1 = __umul24((uint32_t)y1, p2);
       const float top = (1.f - fx) * ldg32(a, o0 + (uint32_t)xi) + fx * ldg32(a, o0 + (uint32_t)x1);
       const float bot = (1.f - fx) * ldg32(a, o1 + (uint32_t)xi) + fx * ldg32(a, o1 + (uint32_t)x1);
       r += fabsf((1.f - fy) * top + fy * bot - (float)y1v[k]);
