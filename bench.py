@@ -697,6 +697,10 @@ def main():
                      "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
+                     # measured HBM rate of the Jacobi launches: counter bytes per launch / HIP-event time
+                     "traffic_GBps": (traffic / (jac_ms / max(jac_n, 1) * 1e-3) / 1e9 if traffic else None),
+                     "traffic_frac_of_8TBps": (traffic / (jac_ms / max(jac_n, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                               if traffic else None),
                      "launches": jac_n, "avg_launch_ms": jac_ms / max(jac_n, 1),
                      "flop_per_px_sweep": FLOP_PER_PX_SWEEP, "px_sweeps": px_sweeps,
                      "streaming_equivalent_GBps": jac_stream_gbs,
