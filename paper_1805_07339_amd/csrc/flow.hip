@@ -121,18 +121,16 @@ __device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const Le
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return min(max(v, lo), hi); }
 
 // Bilinear sample at (X, Y) with X given as integer + fraction (exact
-// positions far from the origin); coordinates clamped to the image.
+// positions far from the origin); coordinates clamped to the image: outside
+// [0, w-2] the x fraction is 0 and x0 is the clamped coordinate (likewise in
+// y).  Branch-free: one unsigned compare decides the fraction and the second
+// column (x0 + 1 inside, else x0 itself, whose weight is then 0).
 template <typename F>
 __device__ __forceinline__ float bilinear_split(F at, int32_t w, int32_t h, int32_t xi, float xf, int32_t yi, float yf) {
-  int32_t x0, y0;
-  float fx, fy;
-  if (xi < 0) { x0 = 0; fx = 0.f; }
-  else if (xi >= w - 1) { x0 = w - 1; fx = 0.f; }
-  else { x0 = xi; fx = xf; }
-  if (yi < 0) { y0 = 0; fy = 0.f; }
-  else if (yi >= h - 1) { y0 = h - 1; fy = 0.f; }
-  else { y0 = yi; fy = yf; }
-  const int32_t x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
+  const bool inx = (uint32_t)xi < (uint32_t)(w - 1), iny = (uint32_t)yi < (uint32_t)(h - 1);
+  const int32_t x0 = clampi(xi, 0, w - 1), y0 = clampi(yi, 0, h - 1);
+  const int32_t x1 = x0 + (inx ? 1 : 0), y1 = y0 + (iny ? 1 : 0);
+  const float fx = inx ? xf : 0.f, fy = iny ? yf : 0.f;
   const float top = (1.f - fx) * at(x0, y0) + fx * at(x1, y0);
   const float bot = (1.f - fx) * at(x0, y1) + fx * at(x1, y1);
   return (1.f - fy) * top + fy * bot;
@@ -309,10 +307,18 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     __syncthreads();
   }
   float rT[IT], rI[IT], rU[IT], rV[IT];
+  // halo element e = tid + 256 i at (ty, tx) = (e / TW, e % TW), advanced
+  // incrementally (256 = 3 TW + 58); elements past the tile repeat the last
+  int hty = (int)threadIdx.x / TW, htx = (int)threadIdx.x % TW;
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
-    const int e = min((int)threadIdx.x + i * 256, NE - 1);
-    const int ty = e / TW, tx = e % TW;
+    if (i > 0) {
+      htx += 256 % TW;
+      hty += 256 / TW;
+      if (htx >= TW) { htx -= TW; ++hty; }
+    }
+    const bool past = hty >= kSetupTH + 2;
+    const int ty = past ? kSetupTH + 1 : hty, tx = past ? TW - 1 : htx;
     const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
     float u0 = 0.f, v0 = 0.f;
     if constexpr (COARSE) {
@@ -360,12 +366,11 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const int xl = (x > 0) ? hx - 1 : hx, xr = (x < g.w - 1) ? hx + 1 : hx;
     const int yu = (y > 0) ? hy - 1 : hy, yd = (y < g.h - 1) ? hy + 1 : hy;
     const float u0 = sU[ly][lx], v0 = sV[ly][lx];
-    const float d1x = (sI[hy][xr] - sI[hy][xl]) * 0.5f;
-    const float d1y = (sI[yd][hx] - sI[yu][hx]) * 0.5f;
-    const float dTx = (sT[hy][xr] - sT[hy][xl]) * 0.5f;
-    const float dTy = (sT[yd][hx] - sT[yu][hx]) * 0.5f;
-    const float Ix = 0.5f * (d1x + dTx);
-    const float Iy = 0.5f * (d1y + dTy);
+    // Ix = (central difference of I1 + that of T) / 2 with each difference
+    // halved: the two power-of-two scalings are folded into one factor 1/4
+    // (exact: scaling by 2^-k commutes with rounding for these magnitudes)
+    const float Ix = ((sI[hy][xr] - sI[hy][xl]) + (sT[hy][xr] - sT[hy][xl])) * 0.25f;
+    const float Iy = ((sI[yd][hx] - sI[yu][hx]) + (sT[yd][hx] - sT[yu][hx])) * 0.25f;
     const float It = sT[hy][hx] - sI[hy][hx];
     const float Itp = It - Ix * u0 - Iy * v0;
     const float den = alpha2 + Ix * Ix + Iy * Iy;
@@ -580,6 +585,7 @@ struct StStep {
   float* dv;
   uint32_t bo0, bo1;  // byte offsets of the lane's two output columns
   bool in0, in1;
+  bool vec;           // wave-uniform: 8-byte accesses (see the kernel)
 
   template <int U, int S>
   __device__ __forceinline__ void sweep(int32_t ii) {
@@ -611,13 +617,24 @@ struct StStep {
         if (r >= y0 && r < y1) {
           float* ru = du + (int64_t)r * w;
           float* rv = dv + (int64_t)r * w;
-          if (in0) {
-            at_off(ru, bo0) = N.x;
-            at_off(rv, bo0) = N.z;
-          }
-          if (in1) {
-            at_off(ru, bo1) = N.y;
-            at_off(rv, bo1) = N.w;
+          if (vec) {
+            // adjacent, 8-byte aligned columns, and in0 == in1 (K, the strip
+            // origin and the width are even on this path): one 8-byte store
+            typedef float nf2 __attribute__((ext_vector_type(2)));
+            typedef __attribute__((address_space(1))) nf2 gnf2;
+            if (in0) {
+              *(gnf2*)&at_off(ru, bo0) = nf2{N.x, N.y};
+              *(gnf2*)&at_off(rv, bo0) = nf2{N.z, N.w};
+            }
+          } else {
+            if (in0) {
+              at_off(ru, bo0) = N.x;
+              at_off(rv, bo0) = N.z;
+            }
+            if (in1) {
+              at_off(ru, bo1) = N.y;
+              at_off(rv, bo1) = N.w;
+            }
           }
         }
         return;
@@ -697,10 +714,11 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   // lanes whose columns are mirrored at the image border read scalars.
   // The float2 path is taken by whole waves (interior strips); a wave with
   // a mirrored border column reads scalars.
-  const bool lane_vec = (g.w % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
+  const bool lane_vec = (g.w % 2 == 0) && (K % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
                         ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
                           reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
-                          reinterpret_cast<uintptr_t>(pc)) % 8 == 0);
+                          reinterpret_cast<uintptr_t>(pc) | reinterpret_cast<uintptr_t>(du) |
+                          reinterpret_cast<uintptr_t>(dv)) % 8 == 0);
   const bool vec = __all(lane_vec);
   const uint32_t bo0 = 4u * (uint32_t)gx0, bo1 = 4u * (uint32_t)gx1;
   auto load_row = [&](int32_t row, float4& uv, float2& a, float2& b, float2& cc) {
@@ -729,7 +747,7 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   float2 na[P], nb[P], nc[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
-  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1};
+  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1, vec};
   static_assert(P % 3 == 0, "prefetch depth must be a multiple of the 3 window slots");
   for (; i <= i_end; i += P) st.template steps<0, P>(i, nuv, na, nb, nc, load_row);
 }

@@ -447,6 +447,125 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_pers(const bf16_t* __re
   }
 }
 
+// Stride-2 layer (conv3: 64 -> 96, its weights are 110 KB) as a persistent
+// kernel: the workgroup stages the weights once in LDS (rows padded to CI + 8
+// channels, so the 16 rows a fragment read touches fall in distinct banks)
+// and then each wave walks tasks of one output row x 16 MR columns on its
+// own: no barrier after the staging.  A fragments come straight from global
+// memory (L2; zero outside the image), requested two (tap, channel-block)
+// steps ahead of their MFMAs; the six B fragments of a step are LDS reads
+// shared by the MR pixel blocks.  Same fragments, MFMA order and epilogue as
+// the tiled kernel, so the output is bitwise the same.
+template <int L, int MR>
+__global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
+                                                      bf16_t* __restrict__ y, CGeom g, int32_t tasks_x,
+                                                      int32_t n_tasks) {
+  constexpr LayerDef D = kNet[L];
+  constexpr int CI = D.ci, CO = D.co, COP = cpad(CO), NB = COP / 16, NCB = CI / 32, WP = CI + 8;
+  constexpr bool RELU = D.relu != 0;
+  static_assert(D.stride == 2 && !D.up && CO % 16 == 0 && CI % 32 == 0, "stride-2 layer");
+  constexpr int NST = 9 * NCB, DEPTH = 3;
+  __shared__ __attribute__((aligned(16))) bf16_t wlds[9 * COP * WP];
+  const int tid = threadIdx.x, lane = tid & 63, r16 = lane & 15, kg = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  {
+    constexpr int NCH = 9 * COP * CI / 8, IT = (NCH + 255) / 256;  // 16-byte chunks
+    const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(L));
+    uint4 reg[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) reg[i] = wsrc[min(tid + i * 256, NCH - 1)];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int c = tid + i * 256;
+      if (c < NCH) *reinterpret_cast<uint4*>(wlds + (c / (CI / 8)) * WP + (c % (CI / 8)) * 8) = reg[i];
+    }
+  }
+  __syncthreads();
+  const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
+  const uint32_t img_bytes = (uint32_t)g.hi * (uint32_t)g.wi * (uint32_t)(CI * 2);
+  const int32_t per_img = g.ho * tasks_x;
+  const int32_t nw = (int32_t)gridDim.x * 4;
+  for (int32_t task = (int32_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wv; task < n_tasks; task += nw) {
+    const int32_t n = task / per_img, rem = task % per_img;
+    const int32_t oy = rem / tasks_x, ox0 = (rem % tasks_x) * (16 * MR);
+    // The image as a buffer resource: an offset past its end reads zeros,
+    // which is the zero padding (no branch around the loads).
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const char*>(x) + (size_t)n * img_bytes), (short)0, (int)img_bytes, 0x00020000);
+    // A fragment of block mr at step st: input pixel (2 oy + ky - 1, 2 ox + kx - 1), channels cb*32 + kg*8 ..
+    auto load_a = [&](int st, bf16x8 (&a)[MR]) {
+      const int tap = st / NCB, cb = st % NCB, ky = tap / 3, kx = tap % 3;
+      const int32_t iy = 2 * oy + ky - 1;
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        const int32_t ix = 2 * (ox0 + 16 * mr + r16) + kx - 1;
+        const bool ok = iy >= 0 && iy < g.hi && ix >= 0 && ix < g.wi;
+        const uint32_t off = ok ? ((uint32_t)(iy * g.wi + ix) * CI + cb * 32 + kg * 8) * 2u : 0x80000000u;
+        a[mr] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+      }
+    };
+    f32x4 acc[MR][NB];
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // A ring of DEPTH steps; the step loop runs DEPTH steps per iteration so
+    // that ring slots stay compile-time registers, and is not unrolled
+    // further (unrolled, the loads of all steps are hoisted and spill); the
+    // last DEPTH steps, which request nothing ahead, are peeled.
+    static_assert(NST % DEPTH == 0 && NST > DEPTH, "step count");
+    bf16x8 abuf[DEPTH][MR];
+    auto mma_step = [&](int st, const bf16x8 (&a)[MR]) {
+      const int tap = st / NCB, cb = st % NCB;
+      bf16x8 b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = ld8(wlds + (tap * COP + nb * 16 + r16) * WP + cb * 32 + kg * 8);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b[nb], a[mr], acc[mr][nb]);
+    };
+#pragma unroll
+    for (int st = 0; st < DEPTH - 1; ++st) load_a(st, abuf[st]);
+#pragma unroll 1
+    for (int sg = 0; sg < NST - DEPTH; sg += DEPTH) {
+#pragma unroll
+      for (int j = 0; j < DEPTH; ++j) {
+        load_a(sg + j + DEPTH - 1, abuf[(j + DEPTH - 1) % DEPTH]);
+        mma_step(sg + j, abuf[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < DEPTH; ++j) {
+      if (j == 0) load_a(NST - 1, abuf[DEPTH - 1]);
+      mma_step(NST - DEPTH + j, abuf[j]);
+    }
+    // epilogue: lane (r16, kg) holds channels nb*16 + 4kg .. +3 of pixel r16 of each block
+    char* yrow = reinterpret_cast<char*>(y) + ((size_t)n * g.ho + oy) * (size_t)g.wo * (CO * 2);  // wave-uniform
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr) {
+      const int32_t ox = ox0 + 16 * mr + r16;
+      if (ox >= g.wo) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + 4 * kg;
+        const float4 bv = *reinterpret_cast<const float4*>(bias + co);
+        float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
+        float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
+        if (RELU) {
+          v0 = fmaxf(v0, 0.f);
+          v1 = fmaxf(v1, 0.f);
+          v2 = fmaxf(v2, 0.f);
+          v3 = fmaxf(v3, 0.f);
+        }
+        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+        stg32(reinterpret_cast<u32x2_t*>(yrow), (uint32_t)(ox * CO + co) * 2u,
+              u32x2_t{pack_bf16x2(v0, v1), pack_bf16x2(v2, v3)});
+      }
+    }
+  }
+}
+
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
 // kernel.  A workgroup owns TOH x TOW conv2 outputs; it stages the net-input
 // tile (2 channels, zero outside the image), computes the conv1 outputs that
@@ -1265,7 +1384,35 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
     const int32_t tx = (g.wo + TOW - 1) / TOW, ty = (g.ho + TOH - 1) / TOH;
     const int64_t grid = (int64_t)tx * ty * g.n;
     if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
-    if constexpr (FwdTile<L>::PERS) {
+    if constexpr (L == 2) {
+      // conv3: persistent, weights in LDS, one workgroup per CU
+      constexpr int MR3 = 3;
+      const int32_t tasks_x = (g.wo + 16 * MR3 - 1) / (16 * MR3);
+      const int64_t n_tasks = (int64_t)g.n * g.ho * tasks_x;
+      if (n_tasks > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+      static std::map<int, int> resident3;
+      static std::mutex mu3;
+      int dev = 0, resident = 0;
+      if (hipGetDevice(&dev) != hipSuccess) { set_error("HIP device query failed"); return SCN_EHIP; }
+      {
+        std::lock_guard<std::mutex> lk(mu3);
+        resident = resident3[dev];
+      }
+      if (resident == 0) {
+        int cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_s2_pers<2, MR3>, 256, 0) != hipSuccess) {
+          set_error("HIP device query failed");
+          return SCN_EHIP;
+        }
+        resident = std::max(1, cus * std::max(1, per_cu));
+        std::lock_guard<std::mutex> lk(mu3);
+        resident3[dev] = resident;
+      }
+      const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>((n_tasks + 3) / 4, resident));
+      hipLaunchKernelGGL((k_conv_s2_pers<2, MR3>), dim3((unsigned)wgs), dim3(256), 0, s, x, blob, (bf16_t*)y, g,
+                         tasks_x, (int32_t)n_tasks);
+    } else if constexpr (FwdTile<L>::PERS) {
       // persistent: as many workgroups as the device holds at once (queried
       // once per device)
       static std::map<int, int> resident_by_dev;
