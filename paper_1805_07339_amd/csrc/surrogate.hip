@@ -182,6 +182,23 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // global).  Each wave owns 16 * MR output pixels (MR pixel blocks of 16 along
 // a row) x all output channels; the epilogue adds the bias, applies ReLU and
 // stores 4 consecutive channels per lane.
+// Weights staged in LDS keep the [tap][co][ci] layout with the 16-byte
+// chunks of each row XOR-swizzled: a B fragment read touches 16 consecutive
+// rows at one chunk, and with rows of 2 CI bytes several of those rows would
+// start in the same bank (CI = 96: rows r and r + 4; CI = 64: every second
+// row).  Chunk c of row r is stored at c ^ ((r >> SH) & MASK), where rows
+// that repeat a bank offset (period P = 256 / gcd(256, 2 CI) rows) differ
+// in r >> SH: the 16 rows of a read then hit 16 distinct 4-bank groups.
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+constexpr int log2_i(int v) { return v <= 1 ? 0 : 1 + log2_i(v / 2); }
+template <int CI> struct WSwz {
+  static constexpr int P = 256 / gcd_i(256, 2 * CI);
+  static constexpr int SH = log2_i(P), MASK = 16 / P - 1;
+  static_assert((P & (P - 1)) == 0 && (CI / 8) % (MASK + 1) == 0, "swizzle stays inside the row");
+  // element offset of chunk c8 of row r
+  static __device__ __forceinline__ int off(int r, int c8) { return r * CI + ((c8 ^ ((r >> SH) & MASK)) << 3); }
+};
+
 template <int L, int TOH, int TOW, int NWAVE, int SH, int SW, bool WLDS>
 __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, const bf16_t* __restrict__ wf,
                                               const float* __restrict__ bias, void* __restrict__ y, const CGeom& g,
@@ -196,7 +213,7 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
   const uint32_t blane = 2u * (uint32_t)(r16 * CI + kg * 8);  // lane's byte offset in a fragment row block
   auto bfrag = [&](int tap, int nb, int cb) -> bf16x8 {
     const bf16_t* base = wf + (tap * COP + nb * 16) * CI + cb * 32;  // wave-uniform
-    if constexpr (WLDS) return ld8(base + (r16 * CI + kg * 8));
+    if constexpr (WLDS) return ld8(wf + WSwz<CI>::off(tap * COP + nb * 16 + r16, cb * 4 + kg));
     else return ldg32(reinterpret_cast<const bf16x8*>(base), blane);
   };
   f32x4 acc[MR][NB];
@@ -355,8 +372,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
     treg[i] = ok ? make_uint4(v.x, v.y, v.z, v.w) : make_uint4(0, 0, 0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < WIT; ++i)
-    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+  for (int i = 0; i < WIT; ++i) {
+    const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r
+    if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<CI>::off(c / (CI / 8), c % (CI / 8))) = wreg[i];
+  }
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT;
@@ -431,8 +450,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_pers(const bf16_t* __re
     for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
     load_tile(t);
 #pragma unroll
-    for (int i = 0; i < WIT; ++i)
-      if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+    for (int i = 0; i < WIT; ++i) {
+      const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r
+      if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<CI>::off(c / (CI / 8), c % (CI / 8))) = wreg[i];
+    }
     store_tile(tile);
   }
   __syncthreads();
@@ -632,8 +653,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
   for (int i = 0; i < ITX; ++i)
     if (tid + i * NT < NX) xt[tid + i * NT] = xr[i];
 #pragma unroll
-  for (int i = 0; i < WIT; ++i)
-    if (tid + i * NT < NW8) reinterpret_cast<uint4*>(wlds)[tid + i * NT] = wreg[i];
+  for (int i = 0; i < WIT; ++i) {
+    const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r (conv2: CI = 32)
+    if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<32>::off(c / 4, c % 4)) = wreg[i];
+  }
   __syncthreads();
 
   // per lane: the xt offsets of its four taps (lane group kg covers taps
