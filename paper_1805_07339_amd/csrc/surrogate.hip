@@ -221,7 +221,61 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
   for (int mr = 0; mr < MR; ++mr)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if constexpr (S == 1) {
+  if constexpr (S == 1 && UP) {
+    // x2 nearest-upsampled input: effective index e reads stored index
+    // (e + 1) >> 1, so the nine taps of a pixel touch only two stored rows
+    // (R0 = ti(orow), R2 = ti(orow + 2); tap row 1 reads R0 for odd and R2
+    // for even output rows) and two stored columns (C0 = ti(c), C2 = ti(c + 2);
+    // tap column 1 reads C0 for odd and C2 for even output columns).  The
+    // four distinct fragments of a (block, channel block) are read once: the
+    // R0 pair at tap row 0, the R2 pair at tap row 1; the middle taps are
+    // selects.  Same fragments and MFMA order as the general path below.
+    constexpr int NST = 3 * NCB;  // steps: (ky, channel block)
+    bf16x8 bq[2][3][NB];
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) bq[0][kx][nb] = bfrag(kx, nb, 0);
+    auto ti = [](int e) { return (e + 1) >> 1; };  // effective -> stored tile index
+    const bool odd_col = (r16 & 1) != 0;           // c0 is a multiple of 16
+    bf16x8 f0[NCB][MR][2], f2[NCB][MR][2];          // [cb][mr][C0, C2] of rows R0, R2
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
+      const int ky = st / NCB, cb = st % NCB, cur = st & 1;
+      if (st + 1 < NST) {
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) bq[cur ^ 1][kx][nb] = bfrag(((st + 1) / NCB) * 3 + kx, nb, (st + 1) % NCB);
+      }
+      bf16x8 a0[MR], a1[MR], a2[MR];
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) {
+        const int blk = wv * MR + mr;
+        const int orow = blk / BPR, c0 = (blk % BPR) * 16;
+        if (ky < 2) {  // ky = 0 reads the R0 pair, ky = 1 the R2 pair
+          const int R = ti(orow + 2 * ky);
+          const bf16_t* rowp = tile + (R * SW) * CP + cb * 32 + kg * 8;
+          bf16x8(&f)[2] = ky == 0 ? f0[cb][mr] : f2[cb][mr];
+          f[0] = ld8(rowp + ti(c0 + r16) * CP);
+          f[1] = ld8(rowp + ti(c0 + r16 + 2) * CP);
+        }
+        const bool use_r0 = ky == 0 || (ky == 1 && (orow & 1));
+        const bf16x8 g0 = use_r0 ? f0[cb][mr][0] : f2[cb][mr][0];
+        const bf16x8 g2 = use_r0 ? f0[cb][mr][1] : f2[cb][mr][1];
+        a0[mr] = g0;
+        a2[mr] = g2;
+        a1[mr] = odd_col ? g0 : g2;
+      }
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int mr = 0; mr < MR; ++mr)
+            acc[mr][nb] = mfma(bq[cur][kx][nb], kx == 0 ? a0[mr] : (kx == 1 ? a1[mr] : a2[mr]), acc[mr][nb]);
+    }
+  } else if constexpr (S == 1) {
     // Stride 1: the three taps of a tap row read consecutive pixels of one
     // tile row (one 16-byte LDS read per tap and pixel block).
     constexpr int NST = 3 * NCB;  // steps: (ky, channel block)
