@@ -92,6 +92,35 @@ def test_forward_parity(W, H):
         assert r <= REL_FWD
 
 
+def test_forward_persistent_rounds_are_batch_invariant():
+    """16 pairs of 512 x 384 give every persistent convolution several rounds
+    of tiles per workgroup (conv3: 2, conv4: 3, conv5: 6 on 256 CUs), so the
+    double-buffered tile hand-over and the task walk are exercised.  Each pair
+    of the batch equals the same pair run alone, bit for bit (a pixel's
+    arithmetic does not depend on the batch or on which workgroup takes its
+    tile), and the last pair matches the oracle."""
+    need_gpu()
+    W, H, n = 512, 384, 17
+    scene = synth.layered_scene(31, W, H)
+    frames = [scene.nv12(5 * t) for t in range(n)]
+    tab = table_from_frames(frames, n, list(range(n)), W, H)
+    t = scn.Table.from_tensor(tab, W, H)
+    master, p64 = _master(_params(3))
+    net = scn.net_pack(master)
+    (batch,) = scn.surrogate_infer([scn.Job(t, scn.Sampling.stride(1, 0, n))], net)
+    assert batch.shape == (n - 1, 2, H, W)
+    for k in (0, 7, n - 2):
+        (one,) = scn.surrogate_infer([scn.Job(t, scn.Sampling.range([(k, k + 2)]))], net)
+        assert torch.equal(one[0], batch[k]), k
+    k = n - 2
+    y1 = frame_np(tab, k, W, H, W)[:H]
+    y2 = frame_np(tab, k + 1, W, H, W)[:H]
+    half, _ = S.forward(p64, S.net_input(y1, y2))
+    r = _rel_l2(batch[k].cpu().numpy(), S.flow_full(half))
+    print("512x384 pair %d forward rel L2 %.2e" % (k, r))
+    assert r <= REL_FWD
+
+
 def test_gradient_parity():
     need_gpu()
     W, H = 64, 48
