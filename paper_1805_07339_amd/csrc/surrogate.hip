@@ -1429,10 +1429,10 @@ constexpr int kMR = 2;  // 16-pixel row blocks per wave
 // of the LDS-tiled forward kernel per layer (measured on the 1080p batch):
 // conv4, conv5 and conv6 keep the whole weight tensor in LDS (conv4's 110 KB
 // next to its quarter-size upsampled input tile); conv6 uses a 16 x 32
-// output tile with 8 waves, conv4 8 x 32 with 8 waves (two pixel blocks per
-// wave keep it at two waves per SIMD), conv3 4 x 16 with 2 waves (its
-// stride-2 input tile would otherwise hold the CU's LDS alone), the others
-// 8 x 32 (4 x 32 for stride 2) with 4 waves.  conv4 and conv5 run
+// output tile with 8 waves, conv4 and conv5 8 x 32 with 8 waves (two pixel
+// blocks per wave: conv5 then fits 128 VGPRs and runs four waves per SIMD,
+// 9% faster than four waves of four blocks), the others 8 x 32 (4 x 32 for
+// stride 2) with 4 waves; conv3 has a kernel of its own.  conv4 and conv5 run
 // persistent (one workgroup per resident slot, weights staged once, next
 // input tile loaded while the current one is multiplied); conv6, whose
 // weights are small, is faster with one workgroup per tile.
@@ -1440,7 +1440,7 @@ template <int L> struct FwdTile {
   static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
   static constexpr bool PERS = (L == 3 || L == 4);
   static constexpr int TOH = kNet[L].stride == 2 ? 4 : (L == 5 ? 16 : 8), TOW = L == 2 ? 16 : 32;
-  static constexpr int NWAVE = (L == 5 || L == 3) ? 8 : (L == 2 ? 2 : 4);
+  static constexpr int NWAVE = (L == 5 || L == 3 || L == 4) ? 8 : (L == 2 ? 2 : 4);
 };
 
 constexpr const char* kFwdTimer[kLayers] = {"conv_fwd1", "conv_fwd2", "conv_fwd3", "conv_fwd4", "conv_fwd5",
