@@ -1023,6 +1023,10 @@ __global__ void k_net_input(const FrameDesc* __restrict__ frames, const PairDesc
   *reinterpret_cast<uint32_t*>(x + i * 2) = (uint32_t)out[0] | ((uint32_t)out[1] << 16);
 }
 
+// pixels per thread of the fused upsample + gate kernel (4 ran no faster:
+// more waves per SIMD, but 16% more VALU work per pixel)
+constexpr int kGatePx = 8;
+
 // Bilinear x2 upsampling tap (half-pixel centres, clamped).
 struct UpTap {
   int i0, i1;
@@ -1189,48 +1193,57 @@ __global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float*
 // Full-resolution flow of the network (x2 bilinear of the half-resolution
 // output, written to the pair's output) fused with the gate statistic
 // |I2(x + w) - I1(x)| (clamped bilinear warp of luma), reduced per block.
+template <int PX>
 __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half, const FrameDesc* __restrict__ frames,
                                                  const PairDesc* __restrict__ pairs, float* __restrict__ part,
                                                  int32_t h, int32_t w, int32_t blocks_per_pair) {
-  // each thread: 8 consecutive pixels of one row (W is a multiple of 8)
+  // each thread: PX (4 or 8) consecutive pixels of one row (W is a multiple of 8)
+  static_assert(PX == 4 || PX == 8, "pixels per thread");
   __shared__ float red[4];
   const int32_t W = 2 * w, H = 2 * h;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t p = blk / blocks_per_pair;
-  const int32_t q = (blk % blocks_per_pair) * 256 + threadIdx.x;  // 8-pixel group
+  const int32_t q = (blk % blocks_per_pair) * 256 + threadIdx.x;  // PX-pixel group
   float r = 0.f;
-  if (q < (W / 8) * H) {
-    const int32_t y = q / (W / 8), xb = (q % (W / 8)) * 8;
+  if (q < (W / PX) * H) {
+    const int32_t y = q / (W / PX), xb = (q % (W / PX)) * PX;
     const PairDesc pd = pairs[p];
     const FrameDesc f1 = frames[pd.f1], f2 = frames[pd.f2];
     const float* hp = half + p * (int64_t)h * w * 2;
     const uint8_t* a = f2.y;
     const uint32_t p2 = (uint32_t)f2.pitch;
     const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
-    // the first frame's 8 luma bytes in one load where the row is 8-byte aligned
-    uint8_t y1v[8];
-    if (((reinterpret_cast<uintptr_t>(f1.y) | (uintptr_t)f1.pitch) & 7u) == 0) {
-      typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-      const u32x2_t v8 = ldg32(reinterpret_cast<const u32x2_t*>(row1), (uint32_t)xb);
+    // the first frame's PX luma bytes in one load where the row is aligned
+    uint8_t y1v[PX];
+    if (((reinterpret_cast<uintptr_t>(f1.y) | (uintptr_t)f1.pitch) & (PX - 1)) == 0) {
+      if constexpr (PX == 8) {
+        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+        const u32x2_t v8 = ldg32(reinterpret_cast<const u32x2_t*>(row1), (uint32_t)xb);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        y1v[k] = (uint8_t)(v8.x >> (8 * k));
-        y1v[4 + k] = (uint8_t)(v8.y >> (8 * k));
+        for (int k = 0; k < 4; ++k) {
+          y1v[k] = (uint8_t)(v8.x >> (8 * k));
+          y1v[4 + k] = (uint8_t)(v8.y >> (8 * k));
+        }
+      } else {
+        const uint32_t v4 = ldg32(reinterpret_cast<const uint32_t*>(row1), (uint32_t)xb);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y1v[k] = (uint8_t)(v4 >> (8 * k));
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) y1v[k] = ldg32(row1, (uint32_t)(xb + k));
+      for (int k = 0; k < PX; ++k) y1v[k] = ldg32(row1, (uint32_t)(xb + k));
     }
-    // The 8 pixels read half-resolution columns k-1 .. k+4 (k = xb/2, clamped)
-    // of two rows: 12 loads instead of 32.  Pixel j's taps (up_tap) are
-    // columns (j+1)/2 and (j+1)/2 + 1 of that window; at the clamped image
-    // borders the tap weight of a substituted column is 0, so the values
-    // equal full_flow_at's.
+    // The PX pixels read half-resolution columns k-1 .. k+PX/2 (k = xb/2,
+    // clamped) of two rows: PX + 4 loads instead of 4 PX.  Pixel j's taps
+    // (up_tap) are columns (j+1)/2 and (j+1)/2 + 1 of that window; at the
+    // clamped image borders the tap weight of a substituted column is 0, so
+    // the values equal full_flow_at's.
     const UpTap ty = up_tap(y, h);
     const int32_t k0 = xb / 2 - 1;
-    float2 r0[6], r1[6];
+    constexpr int NCOL = PX / 2 + 2;
+    float2 r0[NCOL], r1[NCOL];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < NCOL; ++c) {
       const int32_t col = min(max(k0 + c, 0), w - 1);
       const f32x2_t t0 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i0 * (uint32_t)w + (uint32_t)col));
       const f32x2_t t1 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i1 * (uint32_t)w + (uint32_t)col));
@@ -1240,10 +1253,10 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
     // Away from the left and right image borders the horizontal taps are
     // fixed: weights 0.75 / 0.25 for even / odd pixels (exact values of
     // up_tap there), so the per-pixel tap arithmetic is skipped.
-    const bool interior = xb > 0 && xb + 8 < W;
-    float fu8[8], fv8[8];
+    const bool interior = xb > 0 && xb + PX < W;
+    float fu8[PX], fv8[PX];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < PX; ++k) {
       const int32_t x = xb + k;
       UpTap tx;
       if (interior) tx.f = (k & 1) ? 0.25f : 0.75f;
@@ -1269,10 +1282,11 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
     }
     float* ou = pd.out + (int64_t)y * W + xb;
     float* ov = ou + (int64_t)W * H;
-    *reinterpret_cast<float4*>(ou) = make_float4(fu8[0], fu8[1], fu8[2], fu8[3]);
-    *reinterpret_cast<float4*>(ou + 4) = make_float4(fu8[4], fu8[5], fu8[6], fu8[7]);
-    *reinterpret_cast<float4*>(ov) = make_float4(fv8[0], fv8[1], fv8[2], fv8[3]);
-    *reinterpret_cast<float4*>(ov + 4) = make_float4(fv8[4], fv8[5], fv8[6], fv8[7]);
+#pragma unroll
+    for (int k = 0; k < PX; k += 4) {
+      *reinterpret_cast<float4*>(ou + k) = make_float4(fu8[k], fu8[k + 1], fu8[k + 2], fu8[k + 3]);
+      *reinterpret_cast<float4*>(ov + k) = make_float4(fv8[k], fv8[k + 1], fv8[k + 2], fv8[k + 3]);
+    }
   }
   // wave reduction, then across the four waves (fixed order: deterministic)
   for (int off = 32; off > 0; off >>= 1) r += __shfl_down(r, off, 64);
@@ -1651,9 +1665,10 @@ scn_status launch_flow_up(const float* half, const PairDesc* pairs, const NetDim
 scn_status launch_up_gate(const float* half, const FrameDesc* frames, const PairDesc* pairs, float* part,
                           const NetDims& d, int64_t n, float tau, uint8_t* active, hipStream_t s) {
   const int32_t W = 2 * d.w, H = 2 * d.h;
-  const int32_t bpp = (int32_t)(((int64_t)(W / 8) * H + 255) / 256);
+  const int32_t bpp = (int32_t)(((int64_t)(W / kGatePx) * H + 255) / 256);
   KernelTimer timer("gate", s);
-  hipLaunchKernelGGL(k_up_gate, dim3((unsigned)(bpp * n)), dim3(256), 0, s, half, frames, pairs, part, d.h, d.w, bpp);
+  hipLaunchKernelGGL(k_up_gate<kGatePx>, dim3((unsigned)(bpp * n)), dim3(256), 0, s, half, frames, pairs, part, d.h,
+                     d.w, bpp);
   SCN_LAUNCHED("upsample + gate launch");
   hipLaunchKernelGGL(k_gate_final, dim3((unsigned)n), dim3(256), 0, s, part, bpp,
                      1.f / ((float)W * H), tau, pairs, active);
@@ -1661,7 +1676,9 @@ scn_status launch_up_gate(const float* half, const FrameDesc* frames, const Pair
   return SCN_OK;
 }
 
-size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) { return align_up((size_t)n * (((size_t)W * H / 8 + 255) / 256 + 1) * 4); }
+size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) {
+  return align_up((size_t)n * (((size_t)W * H / kGatePx + 255) / 256 + 1) * 4);
+}
 
 }  // namespace sg
 
