@@ -59,6 +59,10 @@ struct ChunkPtrs {
   int64_t n_pairs, n_frames;
   const uint8_t* active;   // per pair: compute this pair (NULL: all pairs)
   const uint8_t* factive;  // per frame: some active pair uses it (NULL: all frames)
+  // with a mask: the active pairs in ascending order and their count (device);
+  // the streaming Jacobi walks this list instead of every pair
+  const int32_t* act_list;
+  const int32_t* act_count;
 };
 
 // Every buffer the kernels touch is device global memory.  Pointers read
@@ -677,79 +681,91 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   // wave-uniform from here on: the pair, band, strip, row counters and plane
   // pointers live in SGPRs and their arithmetic runs on the scalar unit
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wv;  // (pair, band, strip)
   const int64_t per_pair = (int64_t)strips * bands;
-  const int64_t pr = unit / per_pair;
-  if (pr >= c.n_pairs) return;
-  if (c.active && !c.active[pr]) return;
-  const int32_t rem = (int32_t)(unit % per_pair);
-  const int32_t band = rem / strips, strip = rem % strips;
-  const int32_t ox = strip * (128 - 2 * K) - K;
-  const int32_t y0 = band * band_h, y1 = min(g.h, y0 + band_h);
-  const int64_t n = (int64_t)g.w * g.h;
-  const float* su = uv_buf(c, pr, src_code, g.n0);
-  const float* sv = su + n;
-  const float* pa = plane(c, pr, kPlaneA, g.n0);
-  const float* pb = plane(c, pr, kPlaneB, g.n0);
-  const float* pc = plane(c, pr, kPlaneC, g.n0);
-  float* du = uv_buf(c, pr, dst_code, g.n0);
-  float* dv = du + n;
-  const int32_t cx0 = ox + 2 * lane, cx1 = cx0 + 1;
-  const int32_t gx0 = reflect(cx0, g.w), gx1 = reflect(cx1, g.w);
-  const bool in0 = (cx0 >= ox + K) && (cx0 < ox + 128 - K) && (cx0 < g.w);
-  const bool in1 = (cx1 >= ox + K) && (cx1 < ox + 128 - K) && (cx1 < g.w);
-
-  // sweep windows: win[s][slot] = (u col0, u col1, v col0, v col1) of sweep s's row with row % 3 == slot
-  float4 win[K][3];
-#pragma unroll
-  for (int s = 0; s < K; ++s)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) win[s][q] = make_float4(0.f, 0.f, 0.f, 0.f);
-
-  int32_t i = y0 - K - 1;
-  i -= ((i % 3) + 3) % 3;  // start on a multiple of 3 so that slots are static
-  const int32_t i_end = y1 - 1 + K;
-  // Rows are read as float2 where a lane's two columns are adjacent and the
-  // pair is 8-byte aligned in every row (even width, even first column);
-  // lanes whose columns are mirrored at the image border read scalars.
-  // The float2 path is taken by whole waves (interior strips); a wave with
-  // a mirrored border column reads scalars.
-  const bool lane_vec = (g.w % 2 == 0) && (K % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
-                        ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
-                          reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
-                          reinterpret_cast<uintptr_t>(pc) | reinterpret_cast<uintptr_t>(du) |
-                          reinterpret_cast<uintptr_t>(dv)) % 8 == 0);
-  const bool vec = __all(lane_vec);
-  const uint32_t bo0 = 4u * (uint32_t)gx0, bo1 = 4u * (uint32_t)gx1;
-  auto load_row = [&](int32_t row, float4& uv, float2& a, float2& b, float2& cc) {
-    const int64_t r = (int64_t)reflect(row, g.h) * g.w;
-    const float *ru = su + r, *rv = sv + r, *ra = pa + r, *rb = pb + r, *rc = pc + r;
-    if (vec) {
-      typedef float nf2 __attribute__((ext_vector_type(2)));
-      typedef __attribute__((address_space(1))) const nf2 gcnf2;
-      const nf2 u2 = *(gcnf2*)&at_off(ru, bo0);
-      const nf2 v2 = *(gcnf2*)&at_off(rv, bo0);
-      const nf2 a2 = *(gcnf2*)&at_off(ra, bo0);
-      const nf2 b2 = *(gcnf2*)&at_off(rb, bo0);
-      const nf2 c2 = *(gcnf2*)&at_off(rc, bo0);
-      uv = make_float4(u2.x, u2.y, v2.x, v2.y);
-      a = make_float2(a2.x, a2.y);
-      b = make_float2(b2.x, b2.y);
-      cc = make_float2(c2.x, c2.y);
+  // A wave takes unit (pair, band, strip) = its index; with an active-pair
+  // list the units index list slots, and the grid (sized for a fraction of
+  // the pairs) strides over them until the list is exhausted.
+  for (int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wv;; unit += (int64_t)gridDim.x * 4) {
+    int64_t pr;
+    if (c.act_list) {
+      const int64_t slot = unit / per_pair;
+      if (slot >= *c.act_count) return;
+      pr = c.act_list[slot];
     } else {
-      uv = make_float4(at_off(ru, bo0), at_off(ru, bo1), at_off(rv, bo0), at_off(rv, bo1));
-      a = make_float2(at_off(ra, bo0), at_off(ra, bo1));
-      b = make_float2(at_off(rb, bo0), at_off(rb, bo1));
-      cc = make_float2(at_off(rc, bo0), at_off(rc, bo1));
+      pr = unit / per_pair;
+      if (pr >= c.n_pairs) return;
+      if (c.active && !c.active[pr]) return;
     }
-  };
-  float4 nuv[P];
-  float2 na[P], nb[P], nc[P];
+    const int32_t rem = (int32_t)(unit % per_pair);
+    const int32_t band = rem / strips, strip = rem % strips;
+    const int32_t ox = strip * (128 - 2 * K) - K;
+    const int32_t y0 = band * band_h, y1 = min(g.h, y0 + band_h);
+    const int64_t n = (int64_t)g.w * g.h;
+    const float* su = uv_buf(c, pr, src_code, g.n0);
+    const float* sv = su + n;
+    const float* pa = plane(c, pr, kPlaneA, g.n0);
+    const float* pb = plane(c, pr, kPlaneB, g.n0);
+    const float* pc = plane(c, pr, kPlaneC, g.n0);
+    float* du = uv_buf(c, pr, dst_code, g.n0);
+    float* dv = du + n;
+    const int32_t cx0 = ox + 2 * lane, cx1 = cx0 + 1;
+    const int32_t gx0 = reflect(cx0, g.w), gx1 = reflect(cx1, g.w);
+    const bool in0 = (cx0 >= ox + K) && (cx0 < ox + 128 - K) && (cx0 < g.w);
+    const bool in1 = (cx1 >= ox + K) && (cx1 < ox + 128 - K) && (cx1 < g.w);
+
+    // sweep windows: win[s][slot] = (u col0, u col1, v col0, v col1) of sweep s's row with row % 3 == slot
+    float4 win[K][3];
 #pragma unroll
-  for (int q = 0; q < P; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
-  StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1, vec};
-  static_assert(P % 3 == 0, "prefetch depth must be a multiple of the 3 window slots");
-  for (; i <= i_end; i += P) st.template steps<0, P>(i, nuv, na, nb, nc, load_row);
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) win[s][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+
+    int32_t i = y0 - K - 1;
+    i -= ((i % 3) + 3) % 3;  // start on a multiple of 3 so that slots are static
+    const int32_t i_end = y1 - 1 + K;
+    // Rows are read as float2 where a lane's two columns are adjacent and the
+    // pair is 8-byte aligned in every row (even width, even first column);
+    // lanes whose columns are mirrored at the image border read scalars.
+    // The float2 path is taken by whole waves (interior strips); a wave with
+    // a mirrored border column reads scalars.
+    const bool lane_vec = (g.w % 2 == 0) && (K % 2 == 0) && (gx1 == gx0 + 1) && (gx0 % 2 == 0) &&
+                          ((reinterpret_cast<uintptr_t>(su) | reinterpret_cast<uintptr_t>(sv) |
+                            reinterpret_cast<uintptr_t>(pa) | reinterpret_cast<uintptr_t>(pb) |
+                            reinterpret_cast<uintptr_t>(pc) | reinterpret_cast<uintptr_t>(du) |
+                            reinterpret_cast<uintptr_t>(dv)) % 8 == 0);
+    const bool vec = __all(lane_vec);
+    const uint32_t bo0 = 4u * (uint32_t)gx0, bo1 = 4u * (uint32_t)gx1;
+    auto load_row = [&](int32_t row, float4& uv, float2& a, float2& b, float2& cc) {
+      const int64_t r = (int64_t)reflect(row, g.h) * g.w;
+      const float *ru = su + r, *rv = sv + r, *ra = pa + r, *rb = pb + r, *rc = pc + r;
+      if (vec) {
+        typedef float nf2 __attribute__((ext_vector_type(2)));
+        typedef __attribute__((address_space(1))) const nf2 gcnf2;
+        const nf2 u2 = *(gcnf2*)&at_off(ru, bo0);
+        const nf2 v2 = *(gcnf2*)&at_off(rv, bo0);
+        const nf2 a2 = *(gcnf2*)&at_off(ra, bo0);
+        const nf2 b2 = *(gcnf2*)&at_off(rb, bo0);
+        const nf2 c2 = *(gcnf2*)&at_off(rc, bo0);
+        uv = make_float4(u2.x, u2.y, v2.x, v2.y);
+        a = make_float2(a2.x, a2.y);
+        b = make_float2(b2.x, b2.y);
+        cc = make_float2(c2.x, c2.y);
+      } else {
+        uv = make_float4(at_off(ru, bo0), at_off(ru, bo1), at_off(rv, bo0), at_off(rv, bo1));
+        a = make_float2(at_off(ra, bo0), at_off(ra, bo1));
+        b = make_float2(at_off(rb, bo0), at_off(rb, bo1));
+        cc = make_float2(at_off(rc, bo0), at_off(rc, bo1));
+      }
+    };
+    float4 nuv[P];
+    float2 na[P], nb[P], nc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) load_row(i + q, nuv[q], na[q], nb[q], nc[q]);
+    StStep<K> st{win, ring[wv], lane, y0, y1, g.w, du, dv, 4u * (uint32_t)cx0, 4u * (uint32_t)cx1, in0, in1, vec};
+    static_assert(P % 3 == 0, "prefetch depth must be a multiple of the 3 window slots");
+    for (; i <= i_end; i += P) st.template steps<0, P>(i, nuv, na, nb, nc, load_row);
+    if (!c.act_list) return;  // one unit per wave without a list
+  }
 }
 
 LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
@@ -780,6 +796,7 @@ constexpr JacobiVariant kVariants[] = {{1, 4, 0, 0},     {8, 16, 0, 0},    {16, 
                                        {4, 16, 0, 0},    {0, 6, 256, 3},   {0, 8, 256, 3},   {0, 10, 256, 3},
                                        {0, 10, 1024, 3}, {0, 10, 256, 6},  {0, 10, 1024, 6}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kDefaultStreaming = 9;  // K <= 10, 6 rows in flight: the masked (fallback) default
 
 struct JacobiChoice {
   int32_t variant;    // index into kVariants
@@ -831,10 +848,12 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     int64_t bh = (int64_t)g.h * strips * n_eff / want;
     bh = std::max<int64_t>(64, std::min<int64_t>(v.band_cap, bh));
     // a tuned band count (the tail of the last round of waves depends on it)
-    if (jc.bands > 0) bh = (g.h + std::min(jc.bands, g.h) - 1) / std::min(jc.bands, g.h);
+    if (jc.bands > 0 && !c.active) bh = (g.h + std::min(jc.bands, g.h) - 1) / std::min(jc.bands, g.h);
     const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
     const int32_t band_h = (g.h + bands - 1) / bands;
-    const int64_t units = (int64_t)strips * bands * n_pairs;
+    // with an active-pair list the grid covers n_eff pairs' units and the
+    // waves stride over the list (an empty list costs one short launch)
+    const int64_t units = (int64_t)strips * bands * (c.act_list ? n_eff : n_pairs);
     const int64_t grid = (units + 3) / 4;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     const dim3 gd((unsigned)grid), bd(256);
@@ -884,7 +903,7 @@ JacobiChoice default_choice(const LevelGeom& g, int32_t iters) {
 // the work to a subset of the chunk's pairs (NULL: all).
 scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
                           const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
-                          hipStream_t s) {
+                          const int32_t* act_list, const int32_t* act_count, hipStream_t s) {
   uint8_t* base = (uint8_t*)ws;
   const float alpha2 = prm.alpha * prm.alpha;
   const int32_t L = plan.levels;
@@ -900,6 +919,8 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
   c.n_frames = ch.n_frames;
   c.active = active;
   c.factive = factive;
+  c.act_list = act_list;
+  c.act_count = act_count;
   // pyramids of every frame slot of the chunk
   for (int32_t l = 1; l < L; ++l) {
     const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
@@ -966,7 +987,7 @@ scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, 
   if (st != SCN_OK) return st;
   for (const FlowGroup& grp : plan.groups)
     for (const FlowChunk& ch : grp.chunks)
-      if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, s)) != SCN_OK) return st;
+      if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, nullptr, nullptr, s)) != SCN_OK) return st;
   return SCN_OK;
 }
 

@@ -1326,6 +1326,30 @@ __global__ void k_mark_frames(const PairDesc* __restrict__ pairs, const uint8_t*
   factive[pairs[p].f2] = 1;
 }
 
+// The active pairs in ascending order and their count (one workgroup): each
+// thread counts a contiguous run of flags, an exclusive scan of the 256
+// counts gives each run's first list position, and the runs are written.
+__global__ void __launch_bounds__(256) k_compact_active(const uint8_t* __restrict__ active, int64_t n_pairs,
+                                                        int32_t* __restrict__ list, int32_t* __restrict__ count) {
+  __shared__ int32_t part[256];
+  const int t = threadIdx.x;
+  const int64_t per = (n_pairs + 255) / 256, b0 = min(n_pairs, (int64_t)t * per), b1 = min(n_pairs, b0 + per);
+  int32_t c = 0;
+  for (int64_t i = b0; i < b1; ++i) c += active[i] != 0;
+  part[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan (Hillis-Steele)
+    const int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t pos = part[t] - c;
+  for (int64_t i = b0; i < b1; ++i)
+    if (active[i]) list[pos++] = (int32_t)i;
+  if (t == 255) *count = part[255];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1684,7 +1708,7 @@ size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) {
 
 scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
                           const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
-                          hipStream_t s);
+                          const int32_t* act_list, const int32_t* act_count, hipStream_t s);
 
 namespace {
 
@@ -1866,8 +1890,12 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
                          fw);
       hipLaunchKernelGGL(sg::k_mark_frames, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pairs, active,
                          factive, n);
+      int32_t* act_list = (int32_t*)(factive + align_up((size_t)ch.n_frames));
+      int32_t* act_count = act_list + align_up((size_t)n);
+      hipLaunchKernelGGL(sg::k_compact_active, dim3(1), dim3(256), 0, s, active, n, act_list, act_count);
       SCN_LAUNCHED("fallback frame marking launch");
-      if ((st = run_flow_chunk(plan, grp, ch, *fallback_p, ws, active, factive, s)) != SCN_OK) return st;
+      if ((st = run_flow_chunk(plan, grp, ch, *fallback_p, ws, active, factive, act_list, act_count, s)) != SCN_OK)
+        return st;
     }
   }
   return SCN_OK;
