@@ -43,6 +43,17 @@ __device__ __forceinline__ bf16x8 pack8(const bf16_t (&v)[8]) {
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+// Forward accumulators start at the bias (the MFMA's C operand), so the
+// epilogue has no separate bias add.
+__device__ __forceinline__ f32x4 bias4(const float* bias, int co) { return *reinterpret_cast<const f32x4*>(bias + co); }
+// ReLU of two BF16 values packed in a dword: a BF16 is negative exactly when
+// its 16-bit pattern is negative as int16, so a packed int16 max with 0 is
+// the ReLU; ReLU commutes with rounding to BF16, so ReLU after packing
+// equals packing after ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), s16x2{0, 0}));
+}
 
 // ---------------------------------------------------------------------------
 // forward: y[m][co] = act(bias[co] + sum_{tap, ci} W[tap][co][ci] x_e(m, tap)[ci])
@@ -75,7 +86,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = bias4(bias, nb * 16 + 4 * kg);
 
   if constexpr (CI == 2) {
     // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3.
@@ -139,22 +150,18 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int co = nb * 16 + 4 * kg;
-      const float4 bv = *reinterpret_cast<const float4*>(bias + co);
-      float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
-      float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
-      if (RELU) {
-        v0 = fmaxf(v0, 0.f);
-        v1 = fmaxf(v1, 0.f);
-        v2 = fmaxf(v2, 0.f);
-        v3 = fmaxf(v3, 0.f);
-      }
+      const f32x4 v = acc[mr][nb];  // bias included
       if constexpr (L == kLayers - 1) {
-        if (co == 0) *reinterpret_cast<float2*>(reinterpret_cast<float*>(y) + m * CO) = make_float2(v0, v1);
+        if (co == 0) *reinterpret_cast<float2*>(reinterpret_cast<float*>(y) + m * CO) = make_float2(v[0], v[1]);
       } else {
         static_assert(L == kLayers - 1 || CO % 4 == 0, "epilogue stores 4 channels per lane");
         uint2 pk;
-        pk.x = pack_bf16x2(v0, v1);
-        pk.y = pack_bf16x2(v2, v3);
+        pk.x = pack_bf16x2(v[0], v[1]);
+        pk.y = pack_bf16x2(v[2], v[3]);
+        if (RELU) {
+          pk.x = relu_bf16x2(pk.x);
+          pk.y = relu_bf16x2(pk.y);
+        }
         *reinterpret_cast<uint2*>(reinterpret_cast<bf16_t*>(y) + m * CO + co) = pk;
       }
     }
@@ -220,7 +227,7 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
 #pragma unroll
   for (int mr = 0; mr < MR; ++mr)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = bias4(bias, nb * 16 + 4 * kg);
   if constexpr (S == 1 && UP) {
     // x2 nearest-upsampled input: effective index e reads stored index
     // (e + 1) >> 1, so the nine taps of a pixel touch only two stored rows
@@ -350,22 +357,18 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int co = nb * 16 + 4 * kg;
-      const float4 bv = *reinterpret_cast<const float4*>(bias + co);
-      float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
-      float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
-      if (RELU) {
-        v0 = fmaxf(v0, 0.f);
-        v1 = fmaxf(v1, 0.f);
-        v2 = fmaxf(v2, 0.f);
-        v3 = fmaxf(v3, 0.f);
-      }
+      const f32x4 v = acc[mr][nb];  // bias included
       if constexpr (L == kLayers - 1) {
-        static_assert(CO == 2, "last layer writes (u, v)");
-        if (co == 0) stg32(reinterpret_cast<f32x2_t*>(yimg), mo, f32x2_t{v0, v1});
+        static_assert(CO == 2 && !RELU, "last layer writes (u, v)");
+        if (co == 0) stg32(reinterpret_cast<f32x2_t*>(yimg), mo, f32x2_t{v[0], v[1]});
       } else {
         uint2 pk;
-        pk.x = pack_bf16x2(v0, v1);
-        pk.y = pack_bf16x2(v2, v3);
+        pk.x = pack_bf16x2(v[0], v[1]);
+        pk.y = pack_bf16x2(v[2], v[3]);
+        if (RELU) {
+          pk.x = relu_bf16x2(pk.x);
+          pk.y = relu_bf16x2(pk.y);
+        }
         typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
         stg32(reinterpret_cast<u32x2_t*>(yimg), mo + 2u * (uint32_t)co, u32x2_t{pk.x, pk.y});
       }
@@ -447,8 +450,8 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
 // the MFMAs of the current one and written to the other LDS buffer after
 // them, so staging overlaps compute, and the weight tensor crosses the
 // memory hierarchy once per workgroup instead of once per tile.
-template <int L, int TOH, int TOW, int NWAVE>
-__global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_pers(const bf16_t* __restrict__ x,
+template <int L, int TOH, int TOW, int NWAVE, int WPE>
+__global__ void __launch_bounds__(64 * NWAVE, WPE) k_conv_fwd_pers(const bf16_t* __restrict__ x,
                                                               const uint8_t* __restrict__ blob, void* __restrict__ y,
                                                               CGeom g, int32_t tiles_x, int32_t tiles_per_img,
                                                               int32_t n_tiles) {
@@ -583,7 +586,7 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
 #pragma unroll
     for (int mr = 0; mr < MR; ++mr)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = bias4(bias, nb * 16 + 4 * kg);
     // A ring of DEPTH steps; the step loop runs DEPTH steps per iteration so
     // that ring slots stay compile-time registers, and is not unrolled
     // further (unrolled, the loads of all steps are hoisted and spill); the
@@ -624,18 +627,14 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int co = nb * 16 + 4 * kg;
-        const float4 bv = *reinterpret_cast<const float4*>(bias + co);
-        float v0 = acc[mr][nb][0] + bv.x, v1 = acc[mr][nb][1] + bv.y;
-        float v2 = acc[mr][nb][2] + bv.z, v3 = acc[mr][nb][3] + bv.w;
+        const f32x4 v = acc[mr][nb];  // bias included
+        uint32_t p0 = pack_bf16x2(v[0], v[1]), p1 = pack_bf16x2(v[2], v[3]);
         if (RELU) {
-          v0 = fmaxf(v0, 0.f);
-          v1 = fmaxf(v1, 0.f);
-          v2 = fmaxf(v2, 0.f);
-          v3 = fmaxf(v3, 0.f);
+          p0 = relu_bf16x2(p0);
+          p1 = relu_bf16x2(p1);
         }
         typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-        stg32(reinterpret_cast<u32x2_t*>(yrow), (uint32_t)(ox * CO + co) * 2u,
-              u32x2_t{pack_bf16x2(v0, v1), pack_bf16x2(v2, v3)});
+        stg32(reinterpret_cast<u32x2_t*>(yrow), (uint32_t)(ox * CO + co) * 2u, u32x2_t{p0, p1});
       }
     }
   }
@@ -722,9 +721,9 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
     const int tap = 4 * kg + j;
     toff[j] = tap < 9 ? (tap / 3) * XW + tap % 3 : -1;
   }
-  float4 bv[2];
+  f32x4 bv[2];
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) bv[nb] = *reinterpret_cast<const float4*>(b1 + nb * 16 + 4 * kg);
+  for (int nb = 0; nb < 2; ++nb) bv[nb] = bias4(b1, nb * 16 + 4 * kg);
   constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16, NIT = (NBK + NWAVE - 1) / NWAVE;
   // unrolled: the LDS reads and MFMAs of successive pixel blocks overlap
 #pragma unroll
@@ -746,12 +745,12 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
     const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
-      const f32x4 acc = mfma(bw[nb], a, f32x4{0.f, 0.f, 0.f, 0.f});
+      const f32x4 acc = mfma(bw[nb], a, bv[nb]);  // bias as the accumulator's start, as in k_conv_fwd<0>
       const int co = nb * 16 + 4 * kg;
       uint2 pk = make_uint2(0u, 0u);
       if (inside) {
-        pk.x = pack_bf16x2(fmaxf(acc[0] + bv[nb].x, 0.f), fmaxf(acc[1] + bv[nb].y, 0.f));
-        pk.y = pack_bf16x2(fmaxf(acc[2] + bv[nb].z, 0.f), fmaxf(acc[3] + bv[nb].w, 0.f));
+        pk.x = relu_bf16x2(pack_bf16x2(acc[0], acc[1]));
+        pk.y = relu_bf16x2(pack_bf16x2(acc[2], acc[3]));
       }
       if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
     }
@@ -1477,6 +1476,9 @@ constexpr int kMR = 2;  // 16-pixel row blocks per wave
 template <int L> struct FwdTile {
   static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
   static constexpr bool PERS = (L == 3 || L == 4);
+  // waves per SIMD the persistent kernel is compiled for (register budget
+  // 512 / WPE): conv5 runs two 8-wave workgroups per CU, conv4 one
+  static constexpr int WPE = L == 4 ? 4 : 2;
   static constexpr int TOH = kNet[L].stride == 2 ? 4 : (L == 5 ? 16 : 8), TOW = L == 2 ? 16 : 32;
   static constexpr int NWAVE = (L == 5 || L == 3 || L == 4) ? 8 : (L == 2 ? 2 : 4);
 };
@@ -1494,7 +1496,7 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
     const int64_t grid = (M + per_wg - 1) / per_wg;
     hipLaunchKernelGGL((k_conv_fwd<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, x, blob, y, g);
   } else {
-    constexpr int TOH = FwdTile<L>::TOH, TOW = FwdTile<L>::TOW, NW = FwdTile<L>::NWAVE;
+    constexpr int TOH = FwdTile<L>::TOH, TOW = FwdTile<L>::TOW, NW = FwdTile<L>::NWAVE, WPE = FwdTile<L>::WPE;
     constexpr bool BL = FwdTile<L>::BLDS;
     const int32_t tx = (g.wo + TOW - 1) / TOW, ty = (g.ho + TOH - 1) / TOH;
     const int64_t grid = (int64_t)tx * ty * g.n;
@@ -1543,7 +1545,7 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_fwd_pers<L, TOH, TOW, NW>, 64 * NW, 0) !=
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv_fwd_pers<L, TOH, TOW, NW, WPE>, 64 * NW, 0) !=
                 hipSuccess) {
           set_error("HIP device query failed");
           return SCN_EHIP;
@@ -1553,7 +1555,7 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
         resident_by_dev[dev] = resident;
       }
       const int64_t wgs = std::min<int64_t>(grid, resident);
-      hipLaunchKernelGGL((k_conv_fwd_pers<L, TOH, TOW, NW>), dim3((unsigned)wgs), dim3(64 * NW), 0, s, x, blob, y, g,
+      hipLaunchKernelGGL((k_conv_fwd_pers<L, TOH, TOW, NW, WPE>), dim3((unsigned)wgs), dim3(64 * NW), 0, s, x, blob, y, g,
                          tx, tx * ty, (int32_t)grid);
     } else {
       hipLaunchKernelGGL((k_conv_fwd_lds<L, TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, x, blob, y,
