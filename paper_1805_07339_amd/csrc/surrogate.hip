@@ -688,8 +688,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
                    ldg32(fa.y, (ry + 1) * pa + rx + 1);
     const int s2 = (int)ldg32(fb.y, ry * pbp + rx) + ldg32(fb.y, ry * pbp + rx + 1) +
                    ldg32(fb.y, (ry + 1) * pbp + rx) + ldg32(fb.y, (ry + 1) * pbp + rx + 1);
-    const uint32_t v = (uint32_t)f2bf((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f)) |
-                       ((uint32_t)f2bf((float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f)) << 16);
+    // (v - 128) / 64 with integer v is exact in BF16: the hardware pack
+    // returns the same bits as f2bf
+    const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
+                                   (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
     xr[i] = ok ? v : 0u;
   }
   const bf16_t* wf1 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(0));
