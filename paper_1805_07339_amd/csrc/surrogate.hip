@@ -1272,13 +1272,20 @@ __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half,
       const float fu = floorf(f.x), fv = floorf(f.y);
       int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
       float fx = f.x - fu, fy = f.y - fv;
-      if (xi < 0) { xi = 0; fx = 0.f; } else if (xi >= W - 1) { xi = W - 1; fx = 0.f; }
+      // Columns: the two samples of a row come from one 2-byte load at
+      // xs = clamp(xi, 0, W - 2) (unaligned global loads are allowed).  Past
+      // the right edge the clamped sample is the second byte with weight 1,
+      // which equals the first byte with weight 0 of the plain clamped form.
+      int32_t xs;
+      if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= W - 1) { xs = W - 2; fx = 1.f; } else { xs = xi; }
       if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
-      const int32_t x1 = min(xi + 1, W - 1), y1 = min(yi + 1, H - 1);
+      const int32_t y1 = min(yi + 1, H - 1);
       // rows < 2^15, pitch <= 2^20 (checked on the host): 24-bit products
       const uint32_t o0 = __umul24((uint32_t)yi, p2), o1 = __umul24((uint32_t)y1, p2);
-      const float top = (1.f - fx) * ldg32(a, o0 + (uint32_t)xi) + fx * ldg32(a, o0 + (uint32_t)x1);
-      const float bot = (1.f - fx) * ldg32(a, o1 + (uint32_t)xi) + fx * ldg32(a, o1 + (uint32_t)x1);
+      const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(a), o0 + (uint32_t)xs);
+      const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(a), o1 + (uint32_t)xs);
+      const float top = (1.f - fx) * (float)(w0 & 0xFFu) + fx * (float)(w0 >> 8);
+      const float bot = (1.f - fx) * (float)(w1 & 0xFFu) + fx * (float)(w1 >> 8);
       r += fabsf((1.f - fy) * top + fy * bot - (float)y1v[k]);
     }
     float* ou = pd.out + (int64_t)y * W + xb;
