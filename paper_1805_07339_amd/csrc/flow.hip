@@ -124,22 +124,6 @@ __device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const Le
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { return min(max(v, lo), hi); }
 
-// Bilinear sample at (X, Y) with X given as integer + fraction (exact
-// positions far from the origin); coordinates clamped to the image: outside
-// [0, w-2] the x fraction is 0 and x0 is the clamped coordinate (likewise in
-// y).  Branch-free: one unsigned compare decides the fraction and the second
-// column (x0 + 1 inside, else x0 itself, whose weight is then 0).
-template <typename F>
-__device__ __forceinline__ float bilinear_split(F at, int32_t w, int32_t h, int32_t xi, float xf, int32_t yi, float yf) {
-  const bool inx = (uint32_t)xi < (uint32_t)(w - 1), iny = (uint32_t)yi < (uint32_t)(h - 1);
-  const int32_t x0 = clampi(xi, 0, w - 1), y0 = clampi(yi, 0, h - 1);
-  const int32_t x1 = x0 + (inx ? 1 : 0), y1 = y0 + (iny ? 1 : 0);
-  const float fx = inx ? xf : 0.f, fy = iny ? yf : 0.f;
-  const float top = (1.f - fx) * at(x0, y0) + fx * at(x1, y0);
-  const float bot = (1.f - fx) * at(x0, y1) + fx * at(x1, y1);
-  return (1.f - fy) * top + fy * bot;
-}
-
 // ---------------------------------------------------------------------------
 // pyramid: level l = even samples of blur5(level l-1), [1,4,6,4,1]/16
 // horizontal then vertical, clamp-to-edge.  A workgroup owns 16 x 64 output
@@ -263,9 +247,40 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     if constexpr (U8) return (float)ldg(y1, __umul24((uint32_t)yy, q1) + (uint32_t)xx);
     else return ldg(f1, 4u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
   };
-  auto at2 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)ldg(y2, __umul24((uint32_t)yy, q2) + (uint32_t)xx);
-    else return ldg(f2, 4u * (__umul24((uint32_t)yy, q2) + (uint32_t)xx));
+  // Warped I2 at (X, Y) = (xi + xf, yi + yf), X given as integer + fraction
+  // (exact far from the origin), clamped bilinear: outside [0, w-2] the x
+  // fraction is 0 at the clamped column (likewise in y).  The two columns of
+  // a row are read by one load (2 bytes at level 0, 8 bytes above; unaligned
+  // global loads are allowed) at xs = clamp(xi, 0, w - 2); past the right
+  // edge the clamped sample is the second element with weight 1, which is
+  // the same value as the clamped column with weight 0.
+  auto warp_sample = [&](int32_t xi, float xf, int32_t yi, float yf) -> float {
+    int32_t xs;
+    float fx;
+    if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= g.w - 1) { xs = g.w - 2; fx = 1.f; } else { xs = xi; fx = xf; }
+    const bool iny = (uint32_t)yi < (uint32_t)(g.h - 1);
+    const int32_t y0 = clampi(yi, 0, g.h - 1), y1 = y0 + (iny ? 1 : 0);
+    const float fy = iny ? yf : 0.f;
+    float a0, b0, a1, b1;
+    if constexpr (U8) {
+      const uint32_t w0 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y0, q2) + (uint32_t)xs);
+      const uint32_t w1 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y1, q2) + (uint32_t)xs);
+      a0 = (float)(w0 & 0xFFu);
+      b0 = (float)(w0 >> 8);
+      a1 = (float)(w1 & 0xFFu);
+      b1 = (float)(w1 >> 8);
+    } else {
+      typedef float f2v __attribute__((ext_vector_type(2)));
+      const f2v r0 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y0, q2) + (uint32_t)xs));
+      const f2v r1 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y1, q2) + (uint32_t)xs));
+      a0 = r0.x;
+      b0 = r0.y;
+      a1 = r1.x;
+      b1 = r1.y;
+    }
+    const float top = (1.f - fx) * a0 + fx * b0;
+    const float bot = (1.f - fx) * a1 + fx * b1;
+    return (1.f - fy) * top + fy * bot;
   };
   // Start flow = 2 * bilinear(coarse flow, x/2, y/2), separably: the
   // horizontal interpolation of the coarse rows under the tile ((oy-1)/2 ..
@@ -336,7 +351,7 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
       v0 = 2.f * ((1.f - fy) * sHV[r0][tx] + fy * sHV[r1][tx]);
     }
     const float fu = floorf(u0), fv = floorf(v0);
-    rT[i] = bilinear_split(at2, g.w, g.h, x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
+    rT[i] = warp_sample(x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
     rI[i] = at1(x, y);
     rU[i] = u0;
     rV[i] = v0;
