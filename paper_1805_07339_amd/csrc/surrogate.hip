@@ -684,10 +684,13 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
     const int yy = xy0 + e / XW, xx = xx0 + e % XW;
     const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
     const uint32_t ry = 2u * (uint32_t)(ok ? yy : 0), rx = 2u * (uint32_t)(ok ? xx : 0);
-    const int s1 = (int)ldg32(fa.y, ry * pa + rx) + ldg32(fa.y, ry * pa + rx + 1) + ldg32(fa.y, (ry + 1) * pa + rx) +
-                   ldg32(fa.y, (ry + 1) * pa + rx + 1);
-    const int s2 = (int)ldg32(fb.y, ry * pbp + rx) + ldg32(fb.y, ry * pbp + rx + 1) +
-                   ldg32(fb.y, (ry + 1) * pbp + rx) + ldg32(fb.y, (ry + 1) * pbp + rx + 1);
+    // 2x2 luma sums; the two bytes of a row come from one 2-byte load
+    auto sum4 = [&](const uint8_t* yp, uint32_t pitch) -> int {
+      const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(yp), ry * pitch + rx);
+      const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(yp), (ry + 1) * pitch + rx);
+      return (int)((w0 & 0xFFu) + (w0 >> 8) + (w1 & 0xFFu) + (w1 >> 8));
+    };
+    const int s1 = sum4(fa.y, pa), s2 = sum4(fb.y, pbp);
     // (v - 128) / 64 with integer v is exact in BF16: the hardware pack
     // returns the same bits as f2bf
     const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
