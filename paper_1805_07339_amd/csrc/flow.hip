@@ -136,7 +136,7 @@ template <bool U8>
 __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, LevelGeom dst, int32_t tiles_x,
                                                   int32_t tiles_per_frame) {
   using T = typename std::conditional<U8, int, float>::type;
-  __shared__ T sIn[kPyrIH][kPyrIW + 1];
+  __shared__ __attribute__((aligned(16))) T sIn[kPyrIH][kPyrIW + 1];
   __shared__ T sH[kPyrIH][kPyrTW];
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t f = blk / tiles_per_frame;
@@ -146,19 +146,46 @@ __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, Le
   const int32_t ix0 = 2 * ox - 2, iy0 = 2 * oy - 2;
   const Img im = level_img(c, (int32_t)f, src);
   constexpr int NIN = kPyrIH * kPyrIW, IT = (NIN + 255) / 256;
-  T v[IT];
+  // Level 0 tiles whose input lies inside the frame read their 35 rows as
+  // 33 four-byte words each (unaligned global loads are allowed; the 132nd
+  // byte lands in the row's padding column), the others byte by byte with
+  // clamped coordinates.
+  const bool words = U8 && ix0 >= 0 && ix0 + 4 * (kPyrIW / 4 + 1) <= src.w && iy0 >= 0 && iy0 + kPyrIH <= src.h;
+  if constexpr (U8) {
+    if (words) {
+      constexpr int WPR = kPyrIW / 4 + 1, NW = kPyrIH * WPR, ITW = (NW + 255) / 256;
+      uint32_t wv[ITW];
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = min((int)threadIdx.x + i * 256, NIN - 1);
-    const int32_t yy = clampi(iy0 + e / kPyrIW, 0, src.h - 1), xx = clampi(ix0 + e % kPyrIW, 0, src.w - 1);
-    const uint32_t off = (uint32_t)yy * (uint32_t)im.pitch + (uint32_t)xx;
-    if constexpr (U8) v[i] = (int)ldg(im.y8, off);
-    else v[i] = ldg(im.f, 4u * off);
+      for (int i = 0; i < ITW; ++i) {
+        const int e = min((int)threadIdx.x + i * 256, NW - 1);
+        const uint32_t off = (uint32_t)(iy0 + e / WPR) * (uint32_t)im.pitch + (uint32_t)(ix0 + 4 * (e % WPR));
+        wv[i] = ldg(reinterpret_cast<const uint32_t*>(im.y8), off);
+      }
+#pragma unroll
+      for (int i = 0; i < ITW; ++i) {
+        const int e = threadIdx.x + i * 256;
+        if (e < NW)
+          *reinterpret_cast<int4*>(&sIn[e / WPR][4 * (e % WPR)]) =
+              make_int4((int)(wv[i] & 0xFFu), (int)((wv[i] >> 8) & 0xFFu), (int)((wv[i] >> 16) & 0xFFu),
+                        (int)(wv[i] >> 24));
+      }
+    }
   }
+  if (!words) {
+    T v[IT];
 #pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = threadIdx.x + i * 256;
-    if (e < NIN) sIn[e / kPyrIW][e % kPyrIW] = v[i];
+    for (int i = 0; i < IT; ++i) {
+      const int e = min((int)threadIdx.x + i * 256, NIN - 1);
+      const int32_t yy = clampi(iy0 + e / kPyrIW, 0, src.h - 1), xx = clampi(ix0 + e % kPyrIW, 0, src.w - 1);
+      const uint32_t off = (uint32_t)yy * (uint32_t)im.pitch + (uint32_t)xx;
+      if constexpr (U8) v[i] = (int)ldg(im.y8, off);
+      else v[i] = ldg(im.f, 4u * off);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = threadIdx.x + i * 256;
+      if (e < NIN) sIn[e / kPyrIW][e % kPyrIW] = v[i];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < kPyrIH * kPyrTW; e += 256) {
