@@ -57,12 +57,14 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
 
 // ---------------------------------------------------------------------------
 // forward: y[m][co] = act(bias[co] + sum_{tap, ci} W[tap][co][ci] x_e(m, tap)[ci])
-// One wave computes 16*MR output pixels x all output channels.
+// conv1 (2 input channels; the other layers use the LDS-tiled kernels): one
+// wave computes 16*MR output pixels x all output channels.
 template <int L, int MR>
 __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, const uint8_t* __restrict__ blob,
                                                   void* __restrict__ y, CGeom g) {
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16;
+  static_assert(CI == 2, "two input channels: K = 18 fits one MFMA K block");
   constexpr bool UP = D.up != 0, RELU = D.relu != 0;
   const bf16_t* wf = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(L));
   const float* bias = reinterpret_cast<const float*>(blob + blob_bias_off(L));
@@ -88,59 +90,32 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mr][nb] = bias4(bias, nb * 16 + 4 * kg);
 
-  if constexpr (CI == 2) {
-    // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3.
-    bf16x8 a[MR];
+  // K = 18 (9 taps x 2 channels) in one block of 32: lane group kg covers taps 4kg .. 4kg+3.
+  bf16x8 a[MR];
 #pragma unroll
-    for (int mr = 0; mr < MR; ++mr) {
-      bf16_t v[8];
+  for (int mr = 0; mr < MR; ++mr) {
+    bf16_t v[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int tap = 4 * kg + j;
-        uint32_t pair = 0;
-        if (tap < 9) {
-          const int iy = poy[mr] * S + tap / 3 - 1, ix = pox[mr] * S + tap % 3 - 1;
-          if (pv[mr] && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
-            const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
-            pair = *reinterpret_cast<const uint32_t*>(x + (((int64_t)pn[mr] * g.hi + sy) * g.wi + sx) * 2);
-          }
-        }
-        v[2 * j] = (bf16_t)(pair & 0xFFFFu);
-        v[2 * j + 1] = (bf16_t)(pair >> 16);
-      }
-      a[mr] = pack8(v);
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 b = ld8(wf + (nb * 16 + r16) * 32 + kg * 8);
-#pragma unroll
-      for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b, a[mr], acc[mr][nb]);
-    }
-  } else {
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ky = tap / 3, kx = tap % 3;
-      int64_t off[MR];
-      bool ok[MR];
-#pragma unroll
-      for (int mr = 0; mr < MR; ++mr) {
-        const int iy = poy[mr] * S + ky - 1, ix = pox[mr] * S + kx - 1;
-        ok[mr] = pv[mr] && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we;
-        const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
-        off[mr] = ok[mr] ? (((int64_t)pn[mr] * g.hi + sy) * g.wi + sx) * CI : 0;
-      }
-#pragma unroll
-      for (int cb = 0; cb < CI / 32; ++cb) {
-        bf16x8 a[MR];
-#pragma unroll
-        for (int mr = 0; mr < MR; ++mr) a[mr] = ok[mr] ? ld8(x + off[mr] + cb * 32 + kg * 8) : zero8();
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const bf16x8 b = ld8(wf + ((int64_t)(tap * COP + nb * 16 + r16) * CI + cb * 32 + kg * 8));
-#pragma unroll
-          for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b, a[mr], acc[mr][nb]);
+    for (int j = 0; j < 4; ++j) {
+      const int tap = 4 * kg + j;
+      uint32_t pair = 0;
+      if (tap < 9) {
+        const int iy = poy[mr] * S + tap / 3 - 1, ix = pox[mr] * S + tap % 3 - 1;
+        if (pv[mr] && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
+          const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+          pair = *reinterpret_cast<const uint32_t*>(x + (((int64_t)pn[mr] * g.hi + sy) * g.wi + sx) * 2);
         }
       }
+      v[2 * j] = (bf16_t)(pair & 0xFFFFu);
+      v[2 * j + 1] = (bf16_t)(pair >> 16);
     }
+    a[mr] = pack8(v);
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const bf16x8 b = ld8(wf + (nb * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr) acc[mr][nb] = mfma(b, a[mr], acc[mr][nb]);
   }
   // lane (r16, kg) holds channels nb*16 + 4kg .. +3 of pixel r16 of each block
 #pragma unroll
