@@ -80,6 +80,20 @@ def test_uneven_jobs_and_slices_one_call():
     assert _maxdiff(fb_out.cpu().numpy(), eb) <= TOL
 
 
+def test_odd_pitch_rows_unaligned():
+    """An odd pitch puts every odd row at an odd address: the level-0
+    pyramid's word loads and the setup's paired-column warp loads then run
+    unaligned; the flow still matches the oracle."""
+    need_gpu()
+    w, h, pitch = 320, 240, 333
+    frames, _ = c1_frames(n=3, w=w, h=h, seed=41)
+    tab = table_from_frames(frames, 3, [0, 1, 2], w, h, pitch=pitch)
+    job = scn.Job(scn.Table.from_tensor(tab, w, h, pitch), scn.Sampling.stride(1, 0, 3))
+    (f,) = scn.flow([job], scn.flow_params(levels=3))
+    exp = _oracle_pairs(tab, [(0, 1), (1, 2)], w, h, pitch, 3)
+    assert _maxdiff(f.cpu().numpy(), exp) <= TOL
+
+
 def test_chunked_workspace_is_bitwise_identical():
     need_gpu()
     frames, _ = c1_frames(n=9, w=128, h=96)

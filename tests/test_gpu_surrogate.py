@@ -219,6 +219,32 @@ def test_gate_routing_and_residual():
         assert torch.equal(mix[k], ref)
 
 
+def test_odd_pitch_forward_and_residual():
+    """Odd pitch: the network input's 2-byte row loads and the gate's
+    paired-column warp loads run unaligned; forward flow and residual still
+    match the oracle, and the open gate returns the network's flow."""
+    need_gpu()
+    W, H, pitch = 64, 48, 75
+    scene = synth.layered_scene(14, W, H, max_disp=4.0)
+    frames = [scene.nv12(t * 3) for t in range(3)]
+    tab = table_from_frames(frames, 3, [0, 1, 2], W, H, pitch=pitch)
+    job = scn.Job(scn.Table.from_tensor(tab, W, H, pitch), scn.Sampling.stride(1, 0, 3))
+    master, p64 = _master(_params(4))
+    net = scn.net_pack(master)
+    (net_only,) = scn.surrogate_infer([job], net)
+    (kept,), (fb,), (res,) = scn.flow_surrogate([job], net, 1e30, scn.flow_params(levels=3))
+    assert fb.cpu().numpy().tolist() == [0, 0]
+    assert torch.equal(kept, net_only)
+    r = res.cpu().numpy()
+    for k in range(2):
+        y1 = frame_np(tab, k, W, H, pitch)[:H, :W]
+        y2 = frame_np(tab, k + 1, W, H, pitch)[:H, :W]
+        half, _ = S.forward(p64, S.net_input(y1, y2))
+        assert _rel_l2(net_only[k].cpu().numpy(), S.flow_full(half)) <= REL_FWD
+        exp = S.warp_residual(y1, y2, net_only[k].cpu().numpy().astype(np.float64))
+        assert abs(r[k] - exp) <= 1e-4 * max(exp, 1.0)
+
+
 def test_trained_network_gain():
     """What training buys.  On held-out pairs of the training family (512x384
     layered scenes, seeds 4,100,000+, 24 and 96 steps apart) the packaged trained
