@@ -670,13 +670,20 @@ def main():
     rgb = torch.empty((400, H, W, 3), dtype=torch.uint8, device=dev)
     ws_c = torch.empty(scn.workspace_bytes(scn.SCN_OP_CONVERT, [jconv]), dtype=torch.uint8, device=dev)
     scn.sample_convert(jconv, out=rgb, stream=stream, ws=ws_c)
+    # shot-boundary cue over the batch's 1199 S[0,1] pairs (threshold: a
+    # quarter of the largest possible distance)
+    ws_d = torch.empty(scn.workspace_bytes(scn.SCN_OP_HIST_DIFF, [jbig]), dtype=torch.uint8, device=dev)
+    diff_thr = 6 * W * H // 4
+    scn.hist_diff(jbig, hbig, diff_thr, stream=stream, ws=ws_d)
     torch.cuda.synchronize()
     scn.timing_enable(True, 1024)
     for _ in range(5):
         scn.hist(jbig, out=hbig, stream=stream, ws=ws_big)
         scn.sample_convert(jconv, out=rgb, stream=stream, ws=ws_c)
+        scn.hist_diff(jbig, hbig, diff_thr, stream=stream, ws=ws_d)
     hist_ms, hist_n = scn.timing_read("hist16")
     conv_ms, conv_n = scn.timing_read("nv12_rgb24")
+    diff_ms, diff_n = scn.timing_read("hist_diff")
     scn.timing_enable(False)
     hist_gbs = (1.5 * W * H + 192) * n_big * hist_n / (hist_ms * 1e-3) / 1e9
     conv_gbs = 4.5 * W * H * 400 * conv_n / (conv_ms * 1e-3) / 1e9
@@ -726,6 +733,10 @@ def main():
                  "frames_per_s": n_big * hist_n / (hist_ms * 1e-3),
                  "counter_GBps": (ctr_kv["hist_bytes_per_launch"] / (hist_ms / max(hist_n, 1) * 1e-3) / 1e9
                                   if "hist_bytes_per_launch" in ctr_kv else None)},
+        "hist_diff": {"pairs_per_launch": n_big - 1, "avg_launch_ms": diff_ms / max(diff_n, 1),
+                      "pairs_per_s": (n_big - 1) * diff_n / (diff_ms * 1e-3) if diff_ms > 0 else None,
+                      "algorithmic_bytes_per_pair": 192 + 5,
+                      "note": "one wave per pair; 237 KB per launch, so launch latency, not HBM, bounds it"},
         "convert_rgb24": {"achieved_GBps": conv_gbs, "frac": conv_gbs / HBM_PEAK_GBS,
                           "avg_launch_ms": conv_ms / max(conv_n, 1), "frames_per_launch": 400,
                           "counter_GBps": (ctr_kv["convert_bytes_per_launch"] / (conv_ms / max(conv_n, 1) * 1e-3) / 1e9

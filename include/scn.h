@@ -127,7 +127,8 @@ enum {
   SCN_OP_FLOW = 2,
   SCN_OP_SURROGATE = 3,        /* scn_flow_surrogate (p = fallback parameters) */
   SCN_OP_SURROGATE_GRADS = 4,  /* scn_surrogate_grads */
-  SCN_OP_SURROGATE_INFER = 5   /* scn_surrogate_infer */
+  SCN_OP_SURROGATE_INFER = 5,  /* scn_surrogate_infer */
+  SCN_OP_HIST_DIFF = 6         /* scn_hist_diff */
 };
 
 /* Number of sampled rows M of a job, or a negative scn_status. */
@@ -140,7 +141,7 @@ int64_t scn_count_pairs(const scn_job* job);
 /* Workspace for an operation (SCN_OP_*) over `n_jobs` jobs: the size for
  * the fastest schedule (SCN_OP_FLOW and SCN_OP_SURROGATE also run in smaller
  * workspaces, down to a minimum, by processing pairs in chunks).  For
- * SCN_OP_CONVERT and SCN_OP_HIST n_jobs must be 1; p is the flow (or
+ * SCN_OP_CONVERT, SCN_OP_HIST and SCN_OP_HIST_DIFF n_jobs must be 1; p is the flow (or
  * fallback) parameters where needed.  Returns 0 on invalid arguments (see
  * scn_last_error). */
 size_t scn_workspace_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p);
@@ -161,6 +162,20 @@ scn_status scn_sample_convert(const scn_job* job, int32_t out_w, int32_t out_h, 
  * hist: device, uint32 [M][3][16] (channel-major), overwritten. */
 scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_bytes,
                     scn_stream_t stream);
+
+/* Shot-boundary cue (Sec. 5.2.3: shot boundaries found from histogram
+ * differences), a stencil S[0,1] over HIST's output (Sec. 3.2): for each
+ * pair of consecutive sampled rows of a slice (the pairs of FLOW; none
+ * crosses a RANGE window), d = sum over the 3 channels and 16 bins of
+ * |h(second row) - h(first row)|, and cut = (d > threshold).
+ * hist: device, uint32 [M][3][16], the output of scn_hist for the same job
+ * (read only).  diff: device, uint32 [P], overwritten.  cut: device, uint8
+ * [P], overwritten, or NULL.  threshold: in pixel counts (d lies in
+ * [0, 6 w h] and is even).  Frames above 715,827,882 pixels are
+ * SCN_EUNSUPPORTED (d would not fit 32 bits).  P = 0 returns SCN_OK with no
+ * work.  ws: scn_workspace_bytes(SCN_OP_HIST_DIFF, &job, 1, NULL) bytes. */
+scn_status scn_hist_diff(const scn_job* job, const uint32_t* hist, uint32_t threshold, uint32_t* diff,
+                         uint8_t* cut, void* ws, size_t ws_bytes, scn_stream_t stream);
 
 /* FLOW (Sec. 3.2 stencil S[0,1], Sec. 5.1.2): dense pyramidal Horn-Schunck
  * optical flow, FP32, between consecutive sampled rows of each slice of

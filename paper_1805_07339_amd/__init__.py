@@ -22,7 +22,7 @@ SCN_OK, SCN_EINVAL, SCN_EUNSUPPORTED, SCN_ENOSPACE, SCN_EHIP = 0, -1, -2, -3, -4
 SCN_STRIDE, SCN_GATHER, SCN_RANGE = 0, 1, 2
 SCN_RGB24, SCN_GRAY8 = 0, 1
 SCN_OP_CONVERT, SCN_OP_HIST, SCN_OP_FLOW, SCN_OP_SURROGATE = 0, 1, 2, 3
-SCN_OP_SURROGATE_GRADS, SCN_OP_SURROGATE_INFER = 4, 5
+SCN_OP_SURROGATE_GRADS, SCN_OP_SURROGATE_INFER, SCN_OP_HIST_DIFF = 4, 5, 6
 
 _STATUS_NAMES = {SCN_EINVAL: "SCN_EINVAL", SCN_EUNSUPPORTED: "SCN_EUNSUPPORTED", SCN_ENOSPACE: "SCN_ENOSPACE",
                  SCN_EHIP: "SCN_EHIP"}
@@ -57,7 +57,7 @@ class CFlowParams(ctypes.Structure):
 
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
-           "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
+           "scn_hist_diff", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
            "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
            "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate"]
 
@@ -86,6 +86,8 @@ def lib() -> ctypes.CDLL:
     L.scn_sample_convert.restype = ctypes.c_int
     L.scn_hist.argtypes = [P(CJob), vp, vp, ctypes.c_size_t, vp]
     L.scn_hist.restype = ctypes.c_int
+    L.scn_hist_diff.argtypes = [P(CJob), vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.scn_hist_diff.restype = ctypes.c_int
     L.scn_flow.argtypes = [P(CJob), ctypes.c_int32, P(CFlowParams), P(vp), vp, ctypes.c_size_t, vp]
     L.scn_flow.restype = ctypes.c_int
     L.scn_ws_forget.argtypes = [vp]
@@ -299,6 +301,29 @@ def hist(job: Job, out: Optional[torch.Tensor] = None, stream=None, ws: Optional
     w = ws if ws is not None else _ws(dev, need)
     _check(lib().scn_hist(ctypes.byref(job.cjob), out.data_ptr(), w.data_ptr(), w.numel(), _stream(stream)))
     return out
+
+
+def hist_diff(job: Job, hist: torch.Tensor, threshold: int, with_cut: bool = True, stream=None,
+              ws: Optional[torch.Tensor] = None):
+    """Shot-boundary cue over the job's S[0,1] pairs from its HIST output
+    `hist` ([M, 3, 16] int32 holding uint32 counts, on the GPU): returns
+    (diff, cut) with diff int64 [P] (the L1 histogram distances) and cut
+    uint8 [P] (diff > threshold), or cut None when with_cut is False."""
+    p = count_pairs(job)
+    dev = hist.device
+    if not (0 <= int(threshold) <= 0xFFFFFFFF):
+        raise ValueError("threshold must fit uint32")
+    if hist.dtype != torch.int32 or not hist.is_contiguous() or hist.shape != (count_rows(job), 3, 16):
+        raise ValueError("hist must be a contiguous int32 [M, 3, 16] tensor")
+    raw = torch.empty((p,), dtype=torch.int32, device=dev)
+    cut = torch.empty((p,), dtype=torch.uint8, device=dev) if with_cut else None
+    if p > 0:
+        need = workspace_bytes(SCN_OP_HIST_DIFF, [job])
+        w = ws if ws is not None else _ws(dev, need)
+        _check(lib().scn_hist_diff(ctypes.byref(job.cjob), hist.data_ptr(), int(threshold), raw.data_ptr(),
+                                   cut.data_ptr() if cut is not None else None, w.data_ptr(), w.numel(),
+                                   _stream(stream)))
+    return raw.to(torch.int64) & 0xFFFFFFFF, cut
 
 
 def sample_convert(job: Job, out_w: Optional[int] = None, out_h: Optional[int] = None, fmt: int = SCN_RGB24,

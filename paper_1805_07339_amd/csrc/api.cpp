@@ -8,6 +8,8 @@
 
 namespace scn {
 scn_status launch_hist(const scn_table& t, const int64_t* rows_dev, int64_t m, uint32_t* hist, hipStream_t s);
+scn_status launch_hist_diff(const uint32_t* hist, const int32_t* slots_dev, int64_t n_pairs, uint32_t threshold,
+                            uint32_t* diff, uint8_t* cut, hipStream_t s);
 scn_status launch_convert(const scn_table& t, const int64_t* rows_dev, int64_t m, int32_t out_w, int32_t out_h,
                           int32_t fmt, uint8_t* out, hipStream_t s);
 scn_status run_flow(const FlowPlan& plan, const scn_flow_params& p, void* ws, hipStream_t s);
@@ -53,6 +55,15 @@ size_t scn_workspace_bytes(int32_t op, const scn_job* jobs, int32_t n_jobs, cons
     if (resolve_flat(&jobs[0], &r) != SCN_OK) return 0;
     return hist_ws_bytes((int64_t)r.rows.size());
   }
+  if (op == SCN_OP_HIST_DIFF) {
+    if (n_jobs != 1) {
+      set_error("hist diff takes exactly one job");
+      return 0;
+    }
+    Resolved r;
+    if (resolve_flat(&jobs[0], &r) != SCN_OK) return 0;
+    return hist_diff_ws_bytes((int64_t)r.pair_slots.size());
+  }
   if (op == SCN_OP_FLOW) {
     FlowPlan plan;
     if (build_flow_plan(jobs, n_jobs, p, nullptr, /*ws_bytes=*/0, &plan) != SCN_OK) return 0;
@@ -78,6 +89,33 @@ scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_byte
   st = upload_plan(ws, r.rows.data(), r.rows.size() * sizeof(int64_t), s);
   if (st != SCN_OK) return st;
   return launch_hist(*job->table, (const int64_t*)ws, m, hist, s);
+}
+
+scn_status scn_hist_diff(const scn_job* job, const uint32_t* hist, uint32_t threshold, uint32_t* diff, uint8_t* cut,
+                         void* ws, size_t ws_bytes, scn_stream_t stream) {
+  clear_error();
+  Resolved r;
+  scn_status st = resolve_flat(job, &r);
+  if (st != SCN_OK) return st;
+  const int64_t p = (int64_t)r.pair_slots.size();
+  const scn_table& t = *job->table;
+  if ((int64_t)t.width * t.height > kHistDiffMaxPixels) {
+    set_error("frame too large for 32-bit histogram distances");
+    return SCN_EUNSUPPORTED;
+  }
+  if (p == 0) return SCN_OK;
+  if (!hist || !diff) { set_error("hist or diff is NULL"); return SCN_EINVAL; }
+  if (!ws) { set_error("workspace is NULL"); return SCN_EINVAL; }
+  if (ws_bytes < hist_diff_ws_bytes(p)) { set_error("workspace too small for hist diff"); return SCN_ENOSPACE; }
+  std::vector<int32_t> slots((size_t)(2 * p));
+  for (int64_t k = 0; k < p; ++k) {
+    slots[(size_t)(2 * k)] = r.pair_slots[(size_t)k].first;
+    slots[(size_t)(2 * k + 1)] = r.pair_slots[(size_t)k].second;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  st = upload_plan(ws, slots.data(), slots.size() * sizeof(int32_t), s);
+  if (st != SCN_OK) return st;
+  return launch_hist_diff(hist, (const int32_t*)ws, p, threshold, diff, cut, s);
 }
 
 scn_status scn_sample_convert(const scn_job* job, int32_t out_w, int32_t out_h, int32_t fmt, uint8_t* out, void* ws,

@@ -391,6 +391,33 @@ __global__ void __launch_bounds__(kThreads) k_luma_copy(ConvGeom g, const int64_
   out[m * npx + p] = g.frames[rows[m] * g.frame_bytes + (int64_t)y * g.pitch + x];
 }
 
+// Shot-boundary cue: the L1 distance of the [3][16] histograms of the two
+// sampled rows of each S[0,1] pair (Sec. 5.2.3 finds shot boundaries from
+// histogram differences), and the cut flag d > threshold.  One wave per
+// pair: lane b < 48 takes bin b of both histograms and the 48 absolute
+// differences are summed across the wave (an exact integer sum, below 2^32
+// because the host bounds the frame area).
+__global__ void __launch_bounds__(256) k_hist_diff(const uint32_t* __restrict__ hist,
+                                                   const int32_t* __restrict__ slots, int64_t n_pairs,
+                                                   uint32_t threshold, uint32_t* __restrict__ diff,
+                                                   uint8_t* __restrict__ cut) {
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= n_pairs) return;
+  const int64_t i = slots[2 * p], j = slots[2 * p + 1];
+  uint32_t d = 0;
+  if (lane < 48) {
+    const uint32_t a = hist[i * 48 + lane], b = hist[j * 48 + lane];
+    d = a > b ? a - b : b - a;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
+  if (lane == 0) {
+    diff[p] = d;
+    if (cut) cut[p] = d > threshold ? 1 : 0;
+  }
+}
+
 bool vec_ok(const scn_table& t) {
   return ((uintptr_t)t.frames % 16 == 0) && (t.pitch % 16 == 0) && (t.frame_bytes % 16 == 0) && t.width >= 16;
 }
@@ -422,6 +449,17 @@ scn_status launch_hist(const scn_table& t, const int64_t* rows_dev, int64_t m, u
   else
     hipLaunchKernelGGL(k_hist16<false>, dim3((unsigned)grid), dim3(kThreads), 0, s, g, rows_dev, hist);
   SCN_LAUNCHED("hist launch");
+  return SCN_OK;
+}
+
+scn_status launch_hist_diff(const uint32_t* hist, const int32_t* slots_dev, int64_t n_pairs, uint32_t threshold,
+                            uint32_t* diff, uint8_t* cut, hipStream_t s) {
+  const int64_t grid = (n_pairs + 3) / 4;
+  if (grid > 0x7FFFFFFF) { set_error("too many pairs for one launch"); return SCN_EUNSUPPORTED; }
+  KernelTimer timer("hist_diff", s);
+  hipLaunchKernelGGL(k_hist_diff, dim3((unsigned)grid), dim3(256), 0, s, hist, slots_dev, n_pairs, threshold, diff,
+                     cut);
+  SCN_LAUNCHED("hist diff launch");
   return SCN_OK;
 }
 

@@ -145,5 +145,6 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
 }
 
 size_t hist_ws_bytes(int64_t m) { return align_up((size_t)m * sizeof(int64_t)) + kAlign; }
+size_t hist_diff_ws_bytes(int64_t p) { return align_up((size_t)p * 2 * sizeof(int32_t)) + kAlign; }
 
 }  // namespace scn

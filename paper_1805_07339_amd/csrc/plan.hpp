@@ -49,6 +49,10 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t);
 // Workspace layouts -------------------------------------------------------
 // HIST / convert: [plan: int64 rows[M]]
 size_t hist_ws_bytes(int64_t m);
+// HIST diff: [plan: int32 pair positions[P][2]]
+size_t hist_diff_ws_bytes(int64_t p);
+// Largest frame area whose histogram distances (at most 6 w h) fit 32 bits.
+constexpr int64_t kHistDiffMaxPixels = 0xFFFFFFFFLL / 6;
 
 // FLOW: see flow_layout() in flow planning (flow_plan.hpp).
 

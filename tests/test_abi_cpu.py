@@ -91,6 +91,33 @@ def test_hist_validation_before_any_device_work():
     assert L.scn_hist(ctypes.byref(empty.cjob), None, None, 0, None) == scn.SCN_OK
 
 
+def test_hist_diff_validation_before_any_device_work():
+    t = _cpu_table(20)
+    job = scn.Job(t, scn.Sampling.range([(0, 3), (5, 8)]))  # 6 rows, 4 pairs (none across windows)
+    assert scn.count_pairs(job) == 4
+    need = scn.workspace_bytes(scn.SCN_OP_HIST_DIFF, [job])
+    assert need >= 4 * 8
+    L = scn.lib()
+    hist = torch.zeros(6 * 48, dtype=torch.int32)
+    diff = torch.zeros(4, dtype=torch.int32)
+    ws = torch.zeros(need, dtype=torch.uint8)
+    J = ctypes.byref(job.cjob)
+    assert L.scn_hist_diff(J, hist.data_ptr(), 0, diff.data_ptr(), None, ws.data_ptr(), need - 1,
+                           None) == scn.SCN_ENOSPACE
+    assert L.scn_hist_diff(J, None, 0, diff.data_ptr(), None, ws.data_ptr(), need, None) == scn.SCN_EINVAL
+    assert L.scn_hist_diff(J, hist.data_ptr(), 0, None, None, ws.data_ptr(), need, None) == scn.SCN_EINVAL
+    assert L.scn_hist_diff(J, hist.data_ptr(), 0, diff.data_ptr(), None, None, 0, None) == scn.SCN_EINVAL
+    # one row per slice: no pairs, OK with no work
+    single = scn.Job(t, scn.Sampling.gather([4]))
+    assert L.scn_hist_diff(ctypes.byref(single.cjob), None, 0, None, None, None, 0, None) == scn.SCN_OK
+    # frames whose distances could exceed 32 bits are refused
+    big = scn.Table(torch.zeros(1, dtype=torch.uint8), 30000, 30000, 30000, 30000 * 45000, 2)
+    bj = scn.Job(big, scn.Sampling.stride(1, 0, 2))
+    assert L.scn_hist_diff(ctypes.byref(bj.cjob), hist.data_ptr(), 0, diff.data_ptr(), None, ws.data_ptr(), need,
+                           None) == scn.SCN_EUNSUPPORTED
+    assert "32-bit" in scn.lib().scn_last_error().decode()
+
+
 def test_flow_workspace_and_param_validation():
     t = _cpu_table(100, 64, 48)
     job = scn.Job(t, scn.Sampling.stride(10, 0, 100))
