@@ -12,6 +12,14 @@ Readings:
 * Each RANGE window [begin, end) is a slice: no pair crosses two windows.
 * Flow pairs join consecutive *sampled* rows (stencil after sampling); the
   last row of a slice has no successor, so a slice of M rows gives M-1 pairs.
+* Stencil before sampling (Fig. e of Sec. 3.2: flow on original neighbours,
+  then sampled): each sampled row s gives the pair (s, s+1) of original rows;
+  a sampled last row of the table has no successor and gives no pair; RANGE
+  windows do not cut these pairs (the stencil runs on the unsampled
+  sequence).
+* Spacing (the inverse of sampling, Sec. 3.2) of outputs placed at strictly
+  increasing dense positions p_k: NULL fills map[t] = k at t = p_k and -1
+  elsewhere; REPEAT fills map[t] = the last k with p_k <= t (-1 before p_0).
 
 Pins: closed-form enumeration in tests (parity pinned).
 """
@@ -74,4 +82,32 @@ def pairs(kind: str, n_frames: int, **kw) -> List[Tuple[int, int]]:
     out = []
     for s in slices(kind, n_frames, **kw):
         out.extend(zip(s, s[1:]))
+    return out
+
+
+def pairs_before(kind: str, n_frames: int, **kw) -> List[Tuple[int, int]]:
+    """Stencil S[0,1] before sampling: (s, s+1) for every sampled row s with s+1 < n_frames."""
+    return [(r, r + 1) for r in rows(kind, n_frames, **kw) if r + 1 < n_frames]
+
+
+def space_map(positions: Sequence[int], n_dense: int, mode: str) -> List[int]:
+    """Dense index map of outputs placed at strictly increasing positions."""
+    pos = list(positions)
+    for a, b in zip(pos, pos[1:]):
+        if b <= a:
+            raise SamplingError("positions must be strictly increasing")
+    if pos and (pos[0] < 0 or pos[-1] >= n_dense):
+        raise SamplingError("position out of range")
+    out = [-1] * n_dense
+    if mode == "null":
+        for k, t in enumerate(pos):
+            out[t] = k
+    elif mode == "repeat":
+        k = -1
+        for t in range(n_dense):
+            while k + 1 < len(pos) and pos[k + 1] <= t:
+                k += 1
+            out[t] = k
+    else:
+        raise SamplingError("unknown spacing mode")
     return out

@@ -5,6 +5,7 @@ import pytest
 
 import synth
 from oracle import sampling as S
+from oracle import sampling as OS
 
 
 def test_stride_every_24th_of_2400():
@@ -54,3 +55,31 @@ def test_range_240_window_pair_count():
 def test_invalid_specs_raise(kind, kw):
     with pytest.raises(S.SamplingError):
         S.slices(kind, 10, **kw)
+
+
+def test_stencil_before_sampling_pairs():
+    # STRIDE-24 over 2400 frames: (0, 1), (24, 25), ..., (2376, 2377)
+    pb = OS.pairs_before("stride", 2400, start=0, step=24, stop=2400)
+    assert len(pb) == 100 and pb[0] == (0, 1) and pb[-1] == (2376, 2377)
+    assert all(b == a + 1 and a % 24 == 0 for a, b in pb)
+    # a sampled last row of the table has no successor
+    assert OS.pairs_before("gather", 10, idx=[2, 5, 9]) == [(2, 3), (5, 6)]
+    # RANGE windows do not cut the original-neighbour pairs
+    assert OS.pairs_before("range", 10, idx=[0, 2, 4, 6]) == [(0, 1), (1, 2), (4, 5), (5, 6)]
+    # the after-sampling pairs of the same spec differ (low frame rate vs sparse original differences)
+    assert OS.pairs("gather", 10, idx=[2, 5, 9]) == [(2, 5), (5, 9)]
+
+
+def test_spacing_closed_forms():
+    pos = [0, 24, 48]
+    m = OS.space_map(pos, 60, "null")
+    assert [t for t in range(60) if m[t] >= 0] == pos and [m[t] for t in pos] == [0, 1, 2]
+    r = OS.space_map(pos, 60, "repeat")
+    assert r == [0] * 24 + [1] * 24 + [2] * 12
+    assert OS.space_map([3, 5], 7, "repeat") == [-1, -1, -1, 0, 0, 1, 1]
+    # spacing inverts sampling: sampling the spaced sequence at the positions gives 0..K-1
+    for mode in ("null", "repeat"):
+        assert [OS.space_map(pos, 60, mode)[t] for t in pos] == [0, 1, 2]
+    for bad in ([3, 3], [5, 2], [-1], [60]):
+        with pytest.raises(OS.SamplingError):
+            OS.space_map(bad, 60, "null")
