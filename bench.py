@@ -689,6 +689,24 @@ def main():
     conv_gbs = 4.5 * W * H * 400 * conv_n / (conv_ms * 1e-3) / 1e9
     del big, rgb
 
+    # --- stencil before sampling: flow on original neighbours (s, s+1) of the
+    # 100 STRIDE-24 rows (their successors are materialised only now)
+    for r in stride_rows:
+        if r + 1 < N_ROWS:
+            tab[r + 1] = scene.nv12(r + 1, device=dev).reshape(-1)
+    j_before = scn.Job(table, scn.Sampling.stride(24, 0, N_ROWS).before())
+    p_before = scn.count_pairs(j_before)
+    f_before = torch.empty((p_before, 2, H, W), dtype=torch.float32, device=dev)
+    ws_before = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_before], prm), dtype=torch.uint8, device=dev)
+    scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for _ in range(3):
+        scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
+    torch.cuda.synchronize()
+    before_ms = (time.perf_counter() - tb0) * 1e3 / 3
+    del f_before, ws_before
+
     surrogate = (None if args.no_surrogate else
                  surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
     if args.calib_copy:
@@ -733,6 +751,9 @@ def main():
                  "frames_per_s": n_big * hist_n / (hist_ms * 1e-3),
                  "counter_GBps": (ctr_kv["hist_bytes_per_launch"] / (hist_ms / max(hist_n, 1) * 1e-3) / 1e9
                                   if "hist_bytes_per_launch" in ctr_kv else None)},
+        "stencil_before_sampling": {"pairs": p_before, "frames_read": 2 * p_before, "ms_per_call": before_ms,
+                                    "pairs_per_s": p_before / (before_ms * 1e-3),
+                                    "note": "flow of (s, s+1) for the 100 STRIDE-24 rows, no HIST; one call, 3 reps"},
         "hist_diff": {"pairs_per_launch": n_big - 1, "avg_launch_ms": diff_ms / max(diff_n, 1),
                       "pairs_per_s": (n_big - 1) * diff_n / (diff_ms * 1e-3) if diff_ms > 0 else None,
                       "algorithmic_bytes_per_pair": 192 + 5,

@@ -11,13 +11,14 @@
  *   - sampling operations select rows by stride, index list or range
  *     (Sec. 3.2, "Sampling/spacing operations"); ranges also act as slices,
  *     boundaries that reset stencils (Sec. 3.2, "Slicing");
- *   - optical flow is a stencil S[0,1] operation on the sampled sequence
- *     (Sec. 3.2, "Stencil operations"), i.e. between consecutive sampled
- *     rows of one slice;
+ *   - optical flow is a stencil S[0,1] operation (Sec. 3.2, "Stencil
+ *     operations"), by default on the sampled sequence, i.e. between
+ *     consecutive sampled rows of one slice, or on the original sequence
+ *     before sampling (scn_sampling.stencil);
  *   - a job binds an operation to a table and its sampling (Sec. 3.1);
  *   - operations run over batches of elements (Sec. 3.3) and only the
- *     sampled elements are ever read or computed (Sec. 4.2, unneeded element
- *     elimination);
+ *     elements an output needs are ever read or computed (Sec. 4.2, unneeded
+ *     element elimination);
  *   - scratch comes from a caller-owned memory pool (Sec. 4.1, custom GPU
  *     memory pools): no call allocates or frees device memory.
  *
@@ -85,8 +86,20 @@ typedef enum { SCN_STRIDE = 0, SCN_GATHER = 1, SCN_RANGE = 2 } scn_sample_kind;
  *           half-open, ascending and disjoint.  Each window is a slice:
  *           flow pairs never cross two windows.
  * idx is host memory. */
+/* Where the S[0,1] stencil of FLOW sits relative to the sampling (Sec. 3.2,
+ * composing stencils with sampling):
+ *   SCN_STENCIL_AFTER (0): the stencil runs on the sampled sequence; pairs
+ *     join consecutive sampled rows of one slice (flow at a low frame rate).
+ *   SCN_STENCIL_BEFORE (1): the stencil runs on the original sequence and
+ *     its outputs are sampled; each sampled row s gives the pair (s, s+1) of
+ *     original rows (a sparse set of flow fields on original neighbours).  A
+ *     sampled last row of the table gives no pair, and RANGE windows do not
+ *     cut these pairs.  Row s+1 is read though it is not sampled. */
+typedef enum { SCN_STENCIL_AFTER = 0, SCN_STENCIL_BEFORE = 1 } scn_stencil;
+
 typedef struct {
-  int32_t kind, reserved;
+  int32_t kind;
+  int32_t stencil; /* scn_stencil; 0 in zero-initialised specs */
   int64_t start, step, stop;
   const int64_t* idx; /* host */
   int64_t n;
@@ -134,8 +147,8 @@ enum {
 /* Number of sampled rows M of a job, or a negative scn_status. */
 int64_t scn_count_rows(const scn_job* job);
 
-/* Number of flow pairs P of a job (consecutive sampled rows within each
- * slice; Sec. 3.2 stencil after sampling), or a negative scn_status. */
+/* Number of flow pairs P of a job (see scn_stencil), or a negative
+ * scn_status. */
 int64_t scn_count_pairs(const scn_job* job);
 
 /* Workspace for an operation (SCN_OP_*) over `n_jobs` jobs: the size for
@@ -163,11 +176,23 @@ scn_status scn_sample_convert(const scn_job* job, int32_t out_w, int32_t out_h, 
 scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_bytes,
                     scn_stream_t stream);
 
+/* Spacing (Sec. 3.2: the inverse of sampling, which aligns a sampled
+ * sequence with the dense timeline): the index map of the job's FLOW outputs
+ * (its pairs, in order) on the table's n_frames rows, output k placed at the
+ * first row of its pair.  mode SCN_SPACE_NULL: map[t] = k at that row and -1
+ * elsewhere; SCN_SPACE_REPEAT: map[t] = the last output placed at or before
+ * row t (-1 before the first).  map: host, int64 [n_frames], overwritten.
+ * Host only: enqueues nothing. */
+typedef enum { SCN_SPACE_NULL = 0, SCN_SPACE_REPEAT = 1 } scn_space_mode;
+scn_status scn_space_map(const scn_job* job, int32_t mode, int64_t* map);
+
 /* Shot-boundary cue (Sec. 5.2.3: shot boundaries found from histogram
  * differences), a stencil S[0,1] over HIST's output (Sec. 3.2): for each
  * pair of consecutive sampled rows of a slice (the pairs of FLOW; none
  * crosses a RANGE window), d = sum over the 3 channels and 16 bins of
- * |h(second row) - h(first row)|, and cut = (d > threshold).
+ * |h(second row) - h(first row)|, and cut = (d > threshold).  The job's
+ * stencil must be SCN_STENCIL_AFTER (HIST has no output for unsampled rows;
+ * else SCN_EINVAL).
  * hist: device, uint32 [M][3][16], the output of scn_hist for the same job
  * (read only).  diff: device, uint32 [P], overwritten.  cut: device, uint8
  * [P], overwritten, or NULL.  threshold: in pixel counts (d lies in
@@ -178,9 +203,10 @@ scn_status scn_hist_diff(const scn_job* job, const uint32_t* hist, uint32_t thre
                          uint8_t* cut, void* ws, size_t ws_bytes, scn_stream_t stream);
 
 /* FLOW (Sec. 3.2 stencil S[0,1], Sec. 5.1.2): dense pyramidal Horn-Schunck
- * optical flow, FP32, between consecutive sampled rows of each slice of
- * every job.  Jobs may differ in resolution; all of their pairs are
- * computed by one batch of launches.  Each sampled frame's pyramid is built
+ * optical flow, FP32, over the pairs of every job (consecutive sampled rows
+ * of each slice, or original neighbours (s, s+1) of each sampled row s with
+ * SCN_STENCIL_BEFORE).  Jobs may differ in resolution; all of their pairs
+ * are computed by one batch of launches.  Each frame's pyramid is built
  * once and shared by the (at most two) pairs that use it.
  * flow[j]: device, float [P_j][2][H_j][W_j] (u plane then v plane, pixels
  * at full resolution, I1(x) ~ I2(x + (u, v))); may be NULL when P_j == 0. */

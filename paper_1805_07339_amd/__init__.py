@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libscn.so")
 
 SCN_OK, SCN_EINVAL, SCN_EUNSUPPORTED, SCN_ENOSPACE, SCN_EHIP = 0, -1, -2, -3, -4
 SCN_STRIDE, SCN_GATHER, SCN_RANGE = 0, 1, 2
+SCN_STENCIL_AFTER, SCN_STENCIL_BEFORE = 0, 1
+SCN_SPACE_NULL, SCN_SPACE_REPEAT = 0, 1
 SCN_RGB24, SCN_GRAY8 = 0, 1
 SCN_OP_CONVERT, SCN_OP_HIST, SCN_OP_FLOW, SCN_OP_SURROGATE = 0, 1, 2, 3
 SCN_OP_SURROGATE_GRADS, SCN_OP_SURROGATE_INFER, SCN_OP_HIST_DIFF = 4, 5, 6
@@ -41,7 +43,7 @@ class CTable(ctypes.Structure):
 
 
 class CSampling(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("start", ctypes.c_int64),
+    _fields_ = [("kind", ctypes.c_int32), ("stencil", ctypes.c_int32), ("start", ctypes.c_int64),
                 ("step", ctypes.c_int64), ("stop", ctypes.c_int64), ("idx", ctypes.POINTER(ctypes.c_int64)),
                 ("n", ctypes.c_int64)]
 
@@ -57,7 +59,7 @@ class CFlowParams(ctypes.Structure):
 
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
-           "scn_hist_diff", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
+           "scn_hist_diff", "scn_space_map", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
            "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
            "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate"]
 
@@ -88,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.scn_hist.restype = ctypes.c_int
     L.scn_hist_diff.argtypes = [P(CJob), vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_size_t, vp]
     L.scn_hist_diff.restype = ctypes.c_int
+    L.scn_space_map.argtypes = [P(CJob), ctypes.c_int32, vp]
+    L.scn_space_map.restype = ctypes.c_int
     L.scn_flow.argtypes = [P(CJob), ctypes.c_int32, P(CFlowParams), P(vp), vp, ctypes.c_size_t, vp]
     L.scn_flow.restype = ctypes.c_int
     L.scn_ws_forget.argtypes = [vp]
@@ -186,10 +190,18 @@ class Table:
 class Sampling:
     """Stride / gather / range sampling (host-side spec)."""
 
-    def __init__(self, kind: int, start: int = 0, step: int = 1, stop: int = 0, idx: Sequence[int] = ()):
+    def __init__(self, kind: int, start: int = 0, step: int = 1, stop: int = 0, idx: Sequence[int] = (),
+                 stencil: int = SCN_STENCIL_AFTER):
         self.kind, self.start, self.step, self.stop = kind, start, step, stop
+        self.stencil = stencil
         self.idx = [int(v) for v in idx]
         self._arr = (ctypes.c_int64 * max(len(self.idx), 1))(*self.idx)
+
+    def before(self) -> "Sampling":
+        """The same rows with the flow stencil applied before sampling: pairs
+        (s, s+1) of original rows for each sampled row s."""
+        self.stencil = SCN_STENCIL_BEFORE
+        return self
 
     @staticmethod
     def stride(step: int, start: int = 0, stop: Optional[int] = None, n_frames: Optional[int] = None) -> "Sampling":
@@ -210,7 +222,7 @@ class Sampling:
 
     def c(self) -> CSampling:
         n = len(self.idx) // 2 if self.kind == SCN_RANGE else len(self.idx)
-        return CSampling(self.kind, 0, self.start, self.step, self.stop,
+        return CSampling(self.kind, self.stencil, self.start, self.step, self.stop,
                          ctypes.cast(self._arr, ctypes.POINTER(ctypes.c_int64)), n)
 
 
@@ -301,6 +313,16 @@ def hist(job: Job, out: Optional[torch.Tensor] = None, stream=None, ws: Optional
     w = ws if ws is not None else _ws(dev, need)
     _check(lib().scn_hist(ctypes.byref(job.cjob), out.data_ptr(), w.data_ptr(), w.numel(), _stream(stream)))
     return out
+
+
+def space_map(job: Job, mode: int = SCN_SPACE_NULL) -> List[int]:
+    """Spacing: index of the job's FLOW output placed at each table row
+    (NULL: only at the first row of its pair; REPEAT: the last output at or
+    before the row), -1 elsewhere (host only)."""
+    n = job.table.n_frames
+    buf = (ctypes.c_int64 * max(n, 1))()
+    _check(lib().scn_space_map(ctypes.byref(job.cjob), mode, ctypes.cast(buf, ctypes.c_void_p)))
+    return list(buf[:n])
 
 
 def hist_diff(job: Job, hist: torch.Tensor, threshold: int, with_cut: bool = True, stream=None,

@@ -91,12 +91,41 @@ scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_byte
   return launch_hist(*job->table, (const int64_t*)ws, m, hist, s);
 }
 
+scn_status scn_space_map(const scn_job* job, int32_t mode, int64_t* map) {
+  clear_error();
+  Resolved r;
+  scn_status st = resolve_flat(job, &r);
+  if (st != SCN_OK) return st;
+  if (mode != SCN_SPACE_NULL && mode != SCN_SPACE_REPEAT) {
+    set_error("mode must be SCN_SPACE_NULL or SCN_SPACE_REPEAT");
+    return SCN_EINVAL;
+  }
+  const int64_t n = job->table->n_frames;
+  if (n > 0 && !map) { set_error("map is NULL"); return SCN_EINVAL; }
+  for (int64_t t = 0; t < n; ++t) map[t] = -1;
+  const int64_t p = (int64_t)r.pairs.size();
+  for (int64_t k = 0; k < p; ++k) {
+    const int64_t at = r.pairs[(size_t)k].first;  // strictly increasing in k
+    if (mode == SCN_SPACE_NULL) {
+      map[at] = k;
+    } else {
+      const int64_t end = k + 1 < p ? r.pairs[(size_t)(k + 1)].first : n;
+      for (int64_t t = at; t < end; ++t) map[t] = k;
+    }
+  }
+  return SCN_OK;
+}
+
 scn_status scn_hist_diff(const scn_job* job, const uint32_t* hist, uint32_t threshold, uint32_t* diff, uint8_t* cut,
                          void* ws, size_t ws_bytes, scn_stream_t stream) {
   clear_error();
   Resolved r;
   scn_status st = resolve_flat(job, &r);
   if (st != SCN_OK) return st;
+  if (job->sampling->stencil != SCN_STENCIL_AFTER) {
+    set_error("hist diff needs the stencil after sampling (HIST has no output for unsampled rows)");
+    return SCN_EINVAL;
+  }
   const int64_t p = (int64_t)r.pair_slots.size();
   const scn_table& t = *job->table;
   if ((int64_t)t.width * t.height > kHistDiffMaxPixels) {

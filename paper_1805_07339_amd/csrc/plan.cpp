@@ -43,6 +43,10 @@ scn_status resolve(const scn_job* job, std::vector<Slice>* out) {
   if (st != SCN_OK) return st;
   const scn_sampling& s = *job->sampling;
   const int64_t n = job->table->n_frames;
+  if (s.stencil != SCN_STENCIL_AFTER && s.stencil != SCN_STENCIL_BEFORE) {
+    set_error("stencil must be SCN_STENCIL_AFTER or SCN_STENCIL_BEFORE");
+    return SCN_EINVAL;
+  }
   switch (s.kind) {
     case SCN_STRIDE: {
       if (s.step < 1) { set_error("stride step must be >= 1"); return SCN_EINVAL; }
@@ -97,11 +101,20 @@ scn_status resolve_flat(const scn_job* job, Resolved* out) {
   out->rows.clear();
   out->pairs.clear();
   out->pair_slots.clear();
+  const bool before = job->sampling->stencil == SCN_STENCIL_BEFORE;
+  const int64_t n = job->table->n_frames;
   for (const Slice& s : sl) {
     const int32_t base = (int32_t)out->rows.size();
     for (size_t i = 0; i < s.rows.size(); ++i) {
       out->rows.push_back(s.rows[i]);
-      if (i + 1 < s.rows.size()) {
+      if (before) {
+        // stencil on the original sequence: (s, s+1); the successor is not
+        // a sampled row, so it has no slot in the row order
+        if (s.rows[i] + 1 < n) {
+          out->pairs.emplace_back(s.rows[i], s.rows[i] + 1);
+          out->pair_slots.emplace_back(base + (int32_t)i, -1);
+        }
+      } else if (i + 1 < s.rows.size()) {
         out->pairs.emplace_back(s.rows[i], s.rows[i + 1]);
         out->pair_slots.emplace_back(base + (int32_t)i, base + (int32_t)i + 1);
       }

@@ -28,11 +28,13 @@ scn_status check_table(const scn_table* t);
 // slicing).  STRIDE and GATHER give one slice; each RANGE window is a slice.
 scn_status resolve(const scn_job* job, std::vector<Slice>* out);
 
-// Flattened rows (HIST/convert output order) and stencil-after-sampling pairs.
+// Flattened rows (HIST/convert output order) and the S[0,1] pairs: after
+// sampling, consecutive sampled rows of each slice; before sampling, (s, s+1)
+// for each sampled row s with s+1 < n_frames.
 struct Resolved {
   std::vector<int64_t> rows;                    // M sampled rows, output order
-  std::vector<std::pair<int64_t, int64_t>> pairs;  // P pairs (row_i, row_{i+1}) per slice
-  std::vector<std::pair<int32_t, int32_t>> pair_slots;  // indices into rows of each pair
+  std::vector<std::pair<int64_t, int64_t>> pairs;  // P pairs of table rows
+  std::vector<std::pair<int32_t, int32_t>> pair_slots;  // indices into rows of each pair (-1: not a sampled row)
 };
 scn_status resolve_flat(const scn_job* job, Resolved* out);
 

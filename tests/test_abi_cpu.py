@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import paper_1805_07339_amd as scn
+from oracle import sampling as OS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -146,3 +147,44 @@ def test_flow_uneven_jobs_workspace_grows_with_pairs():
     na = scn.workspace_bytes(scn.SCN_OP_FLOW, [a], p)
     nab = scn.workspace_bytes(scn.SCN_OP_FLOW, [a, b], p)
     assert nab > na
+
+
+def test_stencil_before_sampling_pairs_and_validation():
+    t = _cpu_table(2400, 16, 8)
+    jb = scn.Job(t, scn.Sampling.stride(24, 0, 2400).before())
+    assert scn.count_rows(jb) == 100 and scn.count_pairs(jb) == 100
+    t10 = _cpu_table(10, 16, 8)
+    assert scn.count_pairs(scn.Job(t10, scn.Sampling.gather([2, 5, 9]).before())) == 2
+    assert scn.count_pairs(scn.Job(t10, scn.Sampling.gather([2, 5, 9]))) == 2
+    assert scn.count_pairs(scn.Job(t10, scn.Sampling.range([(0, 2), (4, 6)]).before())) == 4
+    assert scn.count_pairs(scn.Job(t10, scn.Sampling.range([(0, 2), (4, 6)]))) == 2
+    bad = scn.Sampling.stride(1, 0, 10)
+    bad.stencil = 2
+    assert scn.lib().scn_count_pairs(ctypes.byref(scn.Job(t10, bad).cjob)) == scn.SCN_EINVAL
+    # HIST has no output for unsampled rows: the shot cue needs the stencil after sampling
+    jg = scn.Job(t10, scn.Sampling.gather([2, 5, 8]).before())
+    hist = torch.zeros(3 * 48, dtype=torch.int32)
+    diff = torch.zeros(3, dtype=torch.int32)
+    ws = torch.zeros(4096, dtype=torch.uint8)
+    assert scn.lib().scn_hist_diff(ctypes.byref(jg.cjob), hist.data_ptr(), 0, diff.data_ptr(), None, ws.data_ptr(),
+                                   4096, None) == scn.SCN_EINVAL
+
+
+@pytest.mark.parametrize("spec", [("stride", dict(start=1, step=7, stop=60)), ("gather", dict(idx=[0, 3, 4, 30, 59])),
+                                  ("range", dict(idx=[2, 6, 10, 11, 40, 47]))])
+def test_space_map_matches_the_oracle(spec):
+    kind, kw = spec
+    n = 60
+    t = _cpu_table(n, 16, 8)
+    mk = {"stride": lambda: scn.Sampling.stride(kw["step"], kw["start"], kw["stop"]),
+          "gather": lambda: scn.Sampling.gather(kw["idx"]),
+          "range": lambda: scn.Sampling.range(list(zip(kw["idx"][0::2], kw["idx"][1::2])))}[kind]
+    for before in (False, True):
+        samp = mk().before() if before else mk()
+        job = scn.Job(t, samp)
+        pairs = OS.pairs_before(kind, n, **kw) if before else OS.pairs(kind, n, **kw)
+        assert scn.count_pairs(job) == len(pairs)
+        pos = [a for a, _ in pairs]
+        for mode, name in ((scn.SCN_SPACE_NULL, "null"), (scn.SCN_SPACE_REPEAT, "repeat")):
+            assert scn.space_map(job, mode) == OS.space_map(pos, n, name)
+    assert scn.lib().scn_space_map(ctypes.byref(scn.Job(t, mk()).cjob), 7, None) == scn.SCN_EINVAL

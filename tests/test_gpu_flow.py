@@ -80,6 +80,33 @@ def test_uneven_jobs_and_slices_one_call():
     assert _maxdiff(fb_out.cpu().numpy(), eb) <= TOL
 
 
+def test_stencil_before_sampling_flow():
+    """Stencil before sampling: each sampled row s gives the pair (s, s+1) of
+    original rows.  Only the sampled rows and their successors hold frames
+    (every other row is poison); the sampled last row of the table has no
+    pair; each pair matches the oracle on its two frames; the same frames as
+    an after-sampling job of consecutive rows give bitwise the same flow."""
+    need_gpu()
+    w, h, n = 160, 120, 40
+    sampled = [3, 17, 25, 39]
+    pairs = OS.pairs_before("gather", n, idx=sampled)
+    assert pairs == [(3, 4), (17, 18), (25, 26)]
+    rows = sorted({r for p in pairs for r in p} | set(sampled))
+    frames, _ = c1_frames(n=len(rows), w=w, h=h, seed=77)
+    tab = table_from_frames(frames, n, rows, w, h)
+    job = scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.gather(sampled).before())
+    assert scn.count_pairs(job) == 3
+    (f,) = scn.flow([job], scn.flow_params(levels=3))
+    assert f.shape == (3, 2, h, w)
+    d = _maxdiff(f.cpu().numpy(), _oracle_pairs(tab, pairs, w, h, w, 3))
+    print("stencil-before max |d| = %.3g" % d, flush=True)
+    assert d <= TOL
+    # pair (17, 18) as a RANGE window of the after-sampling stencil: same work, same bits
+    (g,) = scn.flow([scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.range([(17, 19)]))],
+                    scn.flow_params(levels=3))
+    assert torch.equal(g[0], f[1])
+
+
 def test_odd_pitch_rows_unaligned():
     """An odd pitch puts every odd row at an odd address: the level-0
     pyramid's word loads and the setup's paired-column warp loads then run

@@ -219,6 +219,33 @@ def test_gate_routing_and_residual():
         assert torch.equal(mix[k], ref)
 
 
+def test_stencil_before_sampling_gate_routing():
+    """The surrogate path over original-neighbour pairs (s, s+1): tau = 0
+    returns the plain flow of those pairs bit for bit, tau = inf the
+    network's, and the network's flow matches the oracle's forward."""
+    need_gpu()
+    W, H, n = 64, 48, 12
+    scene = synth.layered_scene(15, W, H, max_disp=4.0)
+    sampled = [2, 6, 9]
+    rows = [2, 3, 6, 7, 9, 10]
+    tab = table_from_frames([scene.nv12(r) for r in rows], n, rows, W, H)
+    job = scn.Job(scn.Table.from_tensor(tab, W, H), scn.Sampling.gather(sampled).before())
+    master, p64 = _master(_params(4))
+    net = scn.net_pack(master)
+    prm = scn.flow_params(levels=3)
+    (plain,) = scn.flow([job], prm)
+    (net_only,) = scn.surrogate_infer([job], net)
+    (all_fb,), (fb1,), _ = scn.flow_surrogate([job], net, 0.0, prm)
+    assert fb1.cpu().numpy().tolist() == [1, 1, 1] and torch.equal(all_fb, plain)
+    (none_fb,), (fb2,), _ = scn.flow_surrogate([job], net, 1e30, prm)
+    assert fb2.cpu().numpy().tolist() == [0, 0, 0] and torch.equal(none_fb, net_only)
+    for k, s in enumerate(sampled):
+        y1 = frame_np(tab, s, W, H, W)[:H, :W]
+        y2 = frame_np(tab, s + 1, W, H, W)[:H, :W]
+        half, _ = S.forward(p64, S.net_input(y1, y2))
+        assert _rel_l2(net_only[k].cpu().numpy(), S.flow_full(half)) <= REL_FWD
+
+
 def test_odd_pitch_forward_and_residual():
     """Odd pitch: the network input's 2-byte row loads and the gate's
     paired-column warp loads run unaligned; forward flow and residual still
