@@ -123,14 +123,23 @@ typedef struct {
  * row by row with variants 5..10 (at most 6, 8, 10, 10, 10, 10 sweeps per
  * launch; variants 8 and 10 stream bands of up to 1024 rows instead of 256;
  * variants 9 and 10 keep six input rows in flight instead of three).  Every
- * schedule gives bitwise identical results. */
+ * schedule gives bitwise identical results.
+ * Temporal warm start (scn_flow only; a bounded-state operation with warmup
+ * W = 1, Sec. 3.2): with `warm_packet` G >= 2 the pairs of each slice are cut
+ * into work packets of G consecutive pairs from the slice's first pair.  The
+ * first pair of a packet is solved cold as above; each later pair is solved
+ * at full resolution only, starting from its predecessor's flow (I2 warped
+ * by it, the constraint linearised about it), with `warm_iters` >= 0 Jacobi
+ * iterations.  Results depend on G, not on batching or chunking.  0 or 1:
+ * every pair cold (warm_iters ignored). */
 typedef struct {
   int32_t levels;
   float alpha;
   int32_t iters;
   int32_t sweeps_per_pass;
   int32_t tile_variant;
-  int32_t reserved;
+  int32_t warm_packet;
+  int32_t warm_iters;
 } scn_flow_params;
 
 enum { SCN_RGB24 = 0, SCN_GRAY8 = 1 };

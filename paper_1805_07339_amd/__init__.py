@@ -54,7 +54,8 @@ class CJob(ctypes.Structure):
 
 class CFlowParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("alpha", ctypes.c_float), ("iters", ctypes.c_int32),
-                ("sweeps_per_pass", ctypes.c_int32), ("tile_variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sweeps_per_pass", ctypes.c_int32), ("tile_variant", ctypes.c_int32), ("warm_packet", ctypes.c_int32),
+                ("warm_iters", ctypes.c_int32)]
 
 
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
@@ -242,8 +243,11 @@ def _jobs_array(jobs: Sequence[Job]):
 
 
 def flow_params(levels: int = 4, alpha: float = 10.0, iters: int = 50, sweeps_per_pass: int = 0,
-                tile_variant: int = 0) -> CFlowParams:
-    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_variant, 0)
+                tile_variant: int = 0, warm_packet: int = 0, warm_iters: int = 0) -> CFlowParams:
+    """Horn-Schunck parameters; warm_packet >= 2 turns on the temporal warm
+    start (packets of that many pairs, later pairs solved at full resolution
+    from their predecessor's flow with warm_iters iterations)."""
+    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_variant, warm_packet, warm_iters)
 
 
 def count_rows(job: Job) -> int:

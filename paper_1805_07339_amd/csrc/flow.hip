@@ -237,7 +237,7 @@ constexpr int kSetupTW = 64, kSetupTH = 16;
 // exists (start flow from it).  Each thread gathers all of its halo-tile
 // samples into registers before the first LDS store, so the loads of one
 // thread overlap instead of waiting one by one.
-template <bool U8, bool COARSE>
+template <bool U8, bool COARSE, bool INIT = false>
 __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
                                                   float alpha2, int32_t tiles_x, int32_t tiles_per_pair) {
   constexpr int TW = kSetupTW + 2, NE = (kSetupTH + 2) * TW, IT = (NE + 255) / 256;
@@ -251,6 +251,8 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   const int32_t t = blk % tiles_per_pair;
   const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
   const PairDesc pd = c.pairs[pr];
+  const float* init_u = INIT ? as_global(pd.init) : nullptr;
+  const float* init_v = INIT ? init_u + (int64_t)g.w * g.h : nullptr;
   const uint8_t* y1 = nullptr;
   const uint8_t* y2 = nullptr;
   const float* f1 = nullptr;
@@ -367,6 +369,12 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const int ty = past ? kSetupTH + 1 : hty, tx = past ? TW - 1 : htx;
     const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
     float u0 = 0.f, v0 = 0.f;
+    if constexpr (INIT) {
+      // warm start: the predecessor pair's full-resolution flow
+      const uint32_t o = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
+      u0 = ldg(init_u, o);
+      v0 = ldg(init_v, o);
+    }
     if constexpr (COARSE) {
       const int32_t yi = y >> 1;
       int32_t y0;
@@ -810,6 +818,44 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   }
 }
 
+// Warm-start schedule: the pairs at position `step` of their work packet
+// (flags, the ordered list of their chunk slots and its length), and for
+// the cold step the frames whose pyramids those pairs need.  One workgroup;
+// chunks hold at most a few thousand pairs.
+__global__ void __launch_bounds__(256) k_warm_step(const PairDesc* __restrict__ pairs, int64_t n_pairs, int32_t step,
+                                                   uint8_t* __restrict__ active, uint8_t* __restrict__ factive,
+                                                   int64_t n_frames, int32_t* __restrict__ list,
+                                                   int32_t* __restrict__ count) {
+  __shared__ int32_t part[256];
+  const int t = threadIdx.x;
+  if (factive)
+    for (int64_t f = t; f < n_frames; f += 256) factive[f] = 0;
+  __syncthreads();
+  const int64_t per = (n_pairs + 255) / 256, b0 = min(n_pairs, (int64_t)t * per), b1 = min(n_pairs, b0 + per);
+  int32_t cnt = 0;
+  for (int64_t i = b0; i < b1; ++i) {
+    const bool a = pairs[i].pos == step;
+    active[i] = a ? 1 : 0;
+    cnt += a ? 1 : 0;
+    if (a && factive) {  // racing stores of the same value
+      factive[pairs[i].f1] = 1;
+      factive[pairs[i].f2] = 1;
+    }
+  }
+  part[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+    const int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t at = part[t] - cnt;
+  for (int64_t i = b0; i < b1; ++i)
+    if (pairs[i].pos == step) list[at++] = (int32_t)i;
+  if (t == 255) *count = part[255];
+}
+
 LevelGeom level_geom(const FlowGroup& grp, int32_t l) {
   LevelGeom g;
   g.w = grp.dims[l].w;
@@ -943,9 +989,12 @@ JacobiChoice default_choice(const LevelGeom& g, int32_t iters) {
 // Flow of one chunk of pairs (pyramids, then coarse-to-fine warp, coef and
 // Jacobi).  `active` / `factive` (device, per pair / per frame slot) restrict
 // the work to a subset of the chunk's pairs (NULL: all).
+// One chunk: pyramids, then per level (coarse to fine) setup and Jacobi.  With
+// `warm`, the active pairs are solved at level 0 only, from their
+// predecessors' flows (PairDesc::init), with prm.iters iterations.
 scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
                           const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
-                          const int32_t* act_list, const int32_t* act_count, hipStream_t s) {
+                          const int32_t* act_list, const int32_t* act_count, hipStream_t s, bool warm) {
   uint8_t* base = (uint8_t*)ws;
   const float alpha2 = prm.alpha * prm.alpha;
   const int32_t L = plan.levels;
@@ -963,8 +1012,9 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
   c.factive = factive;
   c.act_list = act_list;
   c.act_count = act_count;
-  // pyramids of every frame slot of the chunk
-  for (int32_t l = 1; l < L; ++l) {
+  // pyramids of every frame slot of the chunk (a warm solve reads level 0
+  // straight from the table)
+  for (int32_t l = 1; l < (warm ? 1 : L); ++l) {
     const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
     const int32_t tiles_x = (dg.w + kPyrTW - 1) / kPyrTW, tiles_y = (dg.h + kPyrTH - 1) / kPyrTH;
     const int64_t tpf = (int64_t)tiles_x * tiles_y;
@@ -978,7 +1028,7 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
     SCN_LAUNCHED("pyramid launch");
   }
   int32_t result = -1;  // buffer code holding the coarser level's flow
-  for (int32_t l = L - 1; l >= 0; --l) {
+  for (int32_t l = warm ? 0 : L - 1; l >= 0; --l) {
     const LevelGeom g = level_geom(grp, l);
     const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
     const int64_t grid = bpp * ch.n_pairs;
@@ -993,7 +1043,10 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       KernelTimer timer("hs_setup", s);
       const dim3 grid((unsigned)(tpp * ch.n_pairs));
       const bool u8 = g.level == 0, co = g.has_coarse != 0;
-      if (u8 && co)
+      if (warm)
+        hipLaunchKernelGGL((k_hs_setup<true, false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
+                           tiles_x, (int32_t)tpp);
+      else if (u8 && co)
         hipLaunchKernelGGL((k_hs_setup<true, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
                            tiles_x, (int32_t)tpp);
       else if (u8)
@@ -1027,9 +1080,37 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
 scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, hipStream_t s) {
   scn_status st = upload_plan(ws, plan.plan_bytes.data(), plan.plan_bytes.size(), s);
   if (st != SCN_OK) return st;
+  const bool warm = prm.warm_packet >= 2;
+  uint8_t* base = (uint8_t*)ws;
   for (const FlowGroup& grp : plan.groups)
-    for (const FlowChunk& ch : grp.chunks)
-      if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, nullptr, nullptr, s)) != SCN_OK) return st;
+    for (const FlowChunk& ch : grp.chunks) {
+      if (!warm) {
+        if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, nullptr, nullptr, s, false)) != SCN_OK)
+          return st;
+        continue;
+      }
+      // Warm start: step 0 solves the packets' first pairs cold (masked),
+      // step k the pairs at position k from their predecessors' results.  A
+      // predecessor lies in this chunk at step k - 1 or in an earlier chunk,
+      // so stream order is the dependency order.
+      uint8_t* extra = base + plan.scratch_off + chunk_pyr_bytes(grp, ch) + chunk_pairs_bytes(grp, ch);
+      uint8_t* active = extra;
+      uint8_t* factive = active + align_up((size_t)ch.n_pairs);
+      int32_t* list = (int32_t*)(factive + align_up((size_t)ch.n_frames));
+      int32_t* count = list + align_up((size_t)ch.n_pairs * 4) / 4;
+      const PairDesc* pairs = (const PairDesc*)(base + ch.pairs_off);
+      const int32_t steps = ch.max_pos + 1;
+      scn_flow_params wp = prm;
+      wp.iters = prm.warm_iters;
+      for (int32_t k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(k_warm_step, dim3(1), dim3(256), 0, s, pairs, ch.n_pairs, k, active,
+                           k == 0 ? factive : nullptr, ch.n_frames, list, count);
+        SCN_LAUNCHED("warm step marking launch");
+        st = k == 0 ? run_flow_chunk(plan, grp, ch, prm, ws, active, factive, list, count, s, false)
+                    : run_flow_chunk(plan, grp, ch, wp, ws, active, nullptr, list, count, s, true);
+        if (st != SCN_OK) return st;
+      }
+    }
   return SCN_OK;
 }
 

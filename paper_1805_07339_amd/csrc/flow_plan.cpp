@@ -1,5 +1,6 @@
 #include "flow_plan.hpp"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -14,7 +15,11 @@ struct PairRef {
   float* out;
   uint8_t* fb;
   float* resid;
+  const float* init;
+  int32_t pos;
 };
+
+size_t warm_extra(int32_t, int32_t) { return kWarmPairBytes; }
 
 size_t chunk_scratch(const FlowGroup& g, int64_t frames, int64_t pairs) {
   return align_up((size_t)frames * g.pyr_floats * sizeof(float)) +
@@ -38,6 +43,9 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
   scn_status st = check_flow_params(p, nullptr);
   if (st != SCN_OK) return st;
   plan->levels = p->levels;
+  const bool warm = p->warm_packet >= 2;
+  if (warm && extra) { set_error("the warm start applies to scn_flow only"); return SCN_EINVAL; }
+  if (warm) extra = warm_extra;
 
   std::map<std::pair<int32_t, int32_t>, int32_t> group_of;
   std::vector<std::vector<PairRef>> gpairs;
@@ -75,10 +83,15 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
       gi = it->second;
     }
     const size_t fsz = (size_t)2 * t.width * t.height;
-    for (size_t k = 0; k < r.pairs.size(); ++k)
+    int64_t run = 0;  // index of the pair within its slice
+    for (size_t k = 0; k < r.pairs.size(); ++k) {
+      run = (k > 0 && r.pair_slice[k] == r.pair_slice[k - 1]) ? run + 1 : 0;
+      const int32_t pos = warm ? (int32_t)(run % p->warm_packet) : 0;
+      const float* init = (pos > 0 && flow) ? flow[j] + (k - 1) * fsz : nullptr;
       gpairs[gi].push_back(PairRef{j, r.pairs[k].first, r.pairs[k].second, flow ? flow[j] + k * fsz : nullptr,
                                    (fell_back && fell_back[j]) ? fell_back[j] + k : nullptr,
-                                   (residual && residual[j]) ? residual[j] + k : nullptr});
+                                   (residual && residual[j]) ? residual[j] + k : nullptr, init, pos});
+    }
   }
 
   int64_t total = 0;
@@ -135,10 +148,14 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
         d.out = pr.out;
         d.fb = pr.fb;
         d.resid = pr.resid;
+        d.init = pr.init;
+        d.pos = pr.pos;
+        d.pad_ = 0;
         pds.push_back(d);
         ++i;
       }
       FlowChunk c;
+      for (const PairDesc& d : pds) c.max_pos = std::max(c.max_pos, d.pos);
       c.n_frames = (int64_t)fds.size();
       c.n_pairs = (int64_t)pds.size();
       c.frames_off = pb.size();

@@ -22,10 +22,14 @@ struct PairDesc {
   float* out;        // [2][H][W] output (device); the training target for gradient calls
   uint8_t* fb;       // surrogate path: fell-back flag of this pair (device, may be NULL)
   float* resid;      // surrogate path: gate residual of this pair (device, may be NULL)
+  const float* init; // warm start: the predecessor's output flow [2][H][W] (device; NULL for a cold pair)
+  int32_t pos;       // warm start: position in its work packet (0: cold)
+  int32_t pad_;
 };
 
 struct FlowChunk {
   int64_t n_frames = 0, n_pairs = 0;
+  int32_t max_pos = 0;                   // warm start: largest packet position among the chunk's pairs
   size_t frames_off = 0, pairs_off = 0;  // offsets of the descriptor arrays in the plan region
 };
 
@@ -64,6 +68,10 @@ typedef size_t (*ExtraPairBytes)(int32_t w, int32_t h);
 scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_params* p, float* const* flow,
                            size_t ws_bytes, FlowPlan* plan, ExtraPairBytes extra = nullptr,
                            uint8_t* const* fell_back = nullptr, float* const* residual = nullptr);
+
+// Per-pair scratch of the warm-start schedule: step masks, frame marks, the
+// active-pair list and its length (with alignment slack).
+constexpr size_t kWarmPairBytes = 1024;
 
 // Scratch layout of one chunk (offsets from the start of the scratch region).
 size_t chunk_pyr_bytes(const FlowGroup& g, const FlowChunk& c);

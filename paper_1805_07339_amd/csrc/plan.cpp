@@ -101,9 +101,12 @@ scn_status resolve_flat(const scn_job* job, Resolved* out) {
   out->rows.clear();
   out->pairs.clear();
   out->pair_slots.clear();
+  out->pair_slice.clear();
   const bool before = job->sampling->stencil == SCN_STENCIL_BEFORE;
   const int64_t n = job->table->n_frames;
+  int32_t slice = -1;
   for (const Slice& s : sl) {
+    ++slice;
     const int32_t base = (int32_t)out->rows.size();
     for (size_t i = 0; i < s.rows.size(); ++i) {
       out->rows.push_back(s.rows[i]);
@@ -113,10 +116,12 @@ scn_status resolve_flat(const scn_job* job, Resolved* out) {
         if (s.rows[i] + 1 < n) {
           out->pairs.emplace_back(s.rows[i], s.rows[i] + 1);
           out->pair_slots.emplace_back(base + (int32_t)i, -1);
+          out->pair_slice.push_back(slice);
         }
       } else if (i + 1 < s.rows.size()) {
         out->pairs.emplace_back(s.rows[i], s.rows[i + 1]);
         out->pair_slots.emplace_back(base + (int32_t)i, base + (int32_t)i + 1);
+        out->pair_slice.push_back(slice);
       }
     }
   }
@@ -147,6 +152,14 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
     return SCN_EINVAL;
   }
   if (p->tile_variant < 0 || p->tile_variant > 10) { set_error("tile_variant must be in [0, 10]"); return SCN_EINVAL; }
+  if (p->warm_packet < 0 || p->warm_packet > (1 << 20)) {
+    set_error("warm_packet must be in [0, 2^20]");
+    return SCN_EINVAL;
+  }
+  if (p->warm_packet >= 2 && (p->warm_iters < 0 || p->warm_iters > 100000)) {
+    set_error("warm_iters must be in [0, 100000]");
+    return SCN_EINVAL;
+  }
   if (t) {
     auto d = level_dims(t->width, t->height, p->levels);
     if (d.back().w < 2 || d.back().h < 2) {

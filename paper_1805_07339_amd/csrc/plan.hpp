@@ -35,6 +35,7 @@ struct Resolved {
   std::vector<int64_t> rows;                    // M sampled rows, output order
   std::vector<std::pair<int64_t, int64_t>> pairs;  // P pairs of table rows
   std::vector<std::pair<int32_t, int32_t>> pair_slots;  // indices into rows of each pair (-1: not a sampled row)
+  std::vector<int32_t> pair_slice;                       // slice of each pair
 };
 scn_status resolve_flat(const scn_job* job, Resolved* out);
 

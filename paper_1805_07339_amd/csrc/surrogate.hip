@@ -1697,7 +1697,7 @@ size_t gate_part_bytes(int32_t W, int32_t H, int64_t n) {
 
 scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
                           const scn_flow_params& prm, void* ws, const uint8_t* active, const uint8_t* factive,
-                          const int32_t* act_list, const int32_t* act_count, hipStream_t s);
+                          const int32_t* act_list, const int32_t* act_count, hipStream_t s, bool warm);
 
 namespace {
 
@@ -1883,7 +1883,8 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
       int32_t* act_count = act_list + align_up((size_t)n);
       hipLaunchKernelGGL(sg::k_compact_active, dim3(1), dim3(256), 0, s, active, n, act_list, act_count);
       SCN_LAUNCHED("fallback frame marking launch");
-      if ((st = run_flow_chunk(plan, grp, ch, *fallback_p, ws, active, factive, act_list, act_count, s)) != SCN_OK)
+      if ((st = run_flow_chunk(plan, grp, ch, *fallback_p, ws, active, factive, act_list, act_count, s, false)) !=
+          SCN_OK)
         return st;
     }
   }

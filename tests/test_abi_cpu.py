@@ -188,3 +188,17 @@ def test_space_map_matches_the_oracle(spec):
         for mode, name in ((scn.SCN_SPACE_NULL, "null"), (scn.SCN_SPACE_REPEAT, "repeat")):
             assert scn.space_map(job, mode) == OS.space_map(pos, n, name)
     assert scn.lib().scn_space_map(ctypes.byref(scn.Job(t, mk()).cjob), 7, None) == scn.SCN_EINVAL
+
+
+def test_warm_start_params_are_validated():
+    t = _cpu_table(10, 16, 8)
+    job = scn.Job(t, scn.Sampling.stride(1, 0, 10))
+    assert scn.workspace_bytes(scn.SCN_OP_FLOW, [job], scn.flow_params(2, 10.0, 5, warm_packet=4, warm_iters=3)) > \
+        scn.workspace_bytes(scn.SCN_OP_FLOW, [job], scn.flow_params(2, 10.0, 5))
+    L = scn.lib()
+    for bad in (scn.flow_params(2, 10.0, 5, warm_packet=-1), scn.flow_params(2, 10.0, 5, warm_packet=3, warm_iters=-2)):
+        assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, scn._jobs_array([job]), 1, ctypes.byref(bad)) == 0
+        assert "warm" in L.scn_last_error().decode()
+    # the warm start is a FLOW schedule only
+    warm = scn.flow_params(2, 10.0, 5, warm_packet=2, warm_iters=3)
+    assert L.scn_workspace_bytes(scn.SCN_OP_SURROGATE, scn._jobs_array([job]), 1, ctypes.byref(warm)) == 0

@@ -8,6 +8,7 @@ import paper_1805_07339_amd as scn
 import synth
 from oracle import hs as OH
 from oracle import sampling as OS
+from oracle import warm as OW
 from tests.helpers import c1_frames, frame_np, need_gpu, table_from_frames
 
 pytestmark = pytest.mark.gpu
@@ -105,6 +106,49 @@ def test_stencil_before_sampling_flow():
     (g,) = scn.flow([scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.range([(17, 19)]))],
                     scn.flow_params(levels=3))
     assert torch.equal(g[0], f[1])
+
+
+def _constant_motion_frames(n, d, w, h, seed, noise=2.0):
+    rng = synth.SplitMix64(seed)
+    tex = synth.Texture.random(rng)
+    tu = synth.Texture.random(rng, sigma=20.0)
+    tv = synth.Texture.random(rng, sigma=20.0)
+    lay = synth.Layer(tex, tu, tv, "full", shifts=[(t * d[0], t * d[1]) for t in range(n)])
+    sc = synth.Scene(w, h, [lay], seed, noise)
+    return [sc.nv12(t) for t in range(n)]
+
+
+def test_warm_start_chain_matches_the_oracle():
+    """Temporal warm start, packets of 3 pairs over two RANGE slices (pairs
+    0-4 and 6-7): every pair within 1e-3 px of the oracle's chain; a
+    workspace that forces chunking gives the same bits; packets of 1 are
+    the cold solve bit for bit."""
+    need_gpu()
+    w, h, n = 160, 120, 9
+    frames = _constant_motion_frames(n, (0.8, -0.45), w, h, 31)
+    tab = table_from_frames(frames, n, list(range(n)), w, h)
+    job = scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.range([(0, 6), (6, 9)]))
+    prm = scn.flow_params(3, 10.0, 50, warm_packet=3, warm_iters=10)
+    (f,) = scn.flow([job], prm)
+    ys = [frame_np(tab, r, w, h, w)[:h, :w] for r in range(n)]
+    slices = [[(ys[r], ys[r + 1]) for r in range(0, 5)], [(ys[r], ys[r + 1]) for r in range(6, 8)]]
+    exp = OW.warm_chain(slices, 3, 3, 10.0, 50, 10)
+    exp = np.stack([np.stack([u, v]) for u, v in exp])
+    d = _maxdiff(f.cpu().numpy(), exp)
+    print("warm chain max |d| = %.3g" % d, flush=True)
+    assert d <= TOL
+    # the cold pairs of each packet are the plain solve
+    (plain,) = scn.flow([job], scn.flow_params(3, 10.0, 50))
+    for k in (0, 3, 5):
+        assert torch.equal(f[k], plain[k])
+    # chunked workspace: the same bits
+    need = scn.workspace_bytes(scn.SCN_OP_FLOW, [job], prm)
+    small = need // 3
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    (g,) = scn.flow([job], prm, ws=ws, ws_bytes=small)
+    assert torch.equal(f, g)
+    (one,) = scn.flow([job], scn.flow_params(3, 10.0, 50, warm_packet=1, warm_iters=10))
+    assert torch.equal(one, plain)
 
 
 def test_odd_pitch_rows_unaligned():
