@@ -707,6 +707,31 @@ def main():
     before_ms = (time.perf_counter() - tb0) * 1e3 / 3
     del f_before, ws_before
 
+    # --- temporal warm start on 128 consecutive pairs (rows 0..128 of the
+    # same stream): cold pyramid (4 levels x 50 iterations) against packets of 8
+    # whose later pairs run 10 full-resolution iterations from their
+    # predecessor's flow
+    for r in range(0, 129):
+        tab[r] = scene.nv12(r, device=dev).reshape(-1)
+    j_seq = scn.Job(table, scn.Sampling.range([(0, 129)]))
+    p_seq = scn.count_pairs(j_seq)
+    warm_prm = scn.flow_params(LEVELS, ALPHA, ITERS, warm_packet=8, warm_iters=10)
+    f_cold = torch.empty((p_seq, 2, H, W), dtype=torch.float32, device=dev)
+    f_warm = torch.empty_like(f_cold)
+    ws_seq = torch.empty(max(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], prm),
+                             scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], warm_prm)), dtype=torch.uint8, device=dev)
+    seq_ms = {}
+    for name, pp, out in (("cold", prm, f_cold), ("warm", warm_prm, f_warm)):
+        scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        for _ in range(3):
+            scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
+        torch.cuda.synchronize()
+        seq_ms[name] = (time.perf_counter() - ts0) * 1e3 / 3
+    warm_epe = float(torch.sqrt(((f_warm - f_cold) ** 2).sum(dim=1)).mean())
+    del f_cold, f_warm, ws_seq
+
     surrogate = (None if args.no_surrogate else
                  surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
     if args.calib_copy:
@@ -751,6 +776,10 @@ def main():
                  "frames_per_s": n_big * hist_n / (hist_ms * 1e-3),
                  "counter_GBps": (ctr_kv["hist_bytes_per_launch"] / (hist_ms / max(hist_n, 1) * 1e-3) / 1e9
                                   if "hist_bytes_per_launch" in ctr_kv else None)},
+        "warm_start": {"pairs": p_seq, "packet": 8, "warm_iters": 10, "cold_ms_per_call": seq_ms["cold"],
+                       "warm_ms_per_call": seq_ms["warm"], "speedup": seq_ms["cold"] / seq_ms["warm"],
+                       "mean_epe_vs_cold_px": warm_epe,
+                       "note": "128 consecutive 1080p pairs of the stream; flow only"},
         "stencil_before_sampling": {"pairs": p_before, "frames_read": 2 * p_before, "ms_per_call": before_ms,
                                     "pairs_per_s": p_before / (before_ms * 1e-3),
                                     "note": "flow of (s, s+1) for the 100 STRIDE-24 rows, no HIST; one call, 3 reps"},
