@@ -107,6 +107,59 @@ def _conv_flops(W, H):
     return sum(_layer_flops(W, H))
 
 
+def extra_legs(scn, torch, dev, tab, table, scene, stride_rows, prm, stream):
+    """Flow with the stencil before sampling (pairs (s, s+1) of the 100
+    STRIDE-24 rows, whose successors are materialised only now), and the
+    temporal warm start on 128 consecutive pairs (rows 0..128 of the same
+    stream): cold pyramid (4 levels x 50 iterations) against packets of 8
+    whose later pairs run 10 full-resolution iterations from their
+    predecessor's flow."""
+    for r in stride_rows:
+        if r + 1 < N_ROWS:
+            tab[r + 1] = scene.nv12(r + 1, device=dev).reshape(-1)
+    j_before = scn.Job(table, scn.Sampling.stride(24, 0, N_ROWS).before())
+    p_before = scn.count_pairs(j_before)
+    f_before = torch.empty((p_before, 2, H, W), dtype=torch.float32, device=dev)
+    ws_before = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_before], prm), dtype=torch.uint8, device=dev)
+    scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for _ in range(3):
+        scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
+    torch.cuda.synchronize()
+    before_ms = (time.perf_counter() - tb0) * 1e3 / 3
+    del f_before, ws_before
+
+    for r in range(0, 129):
+        tab[r] = scene.nv12(r, device=dev).reshape(-1)
+    j_seq = scn.Job(table, scn.Sampling.range([(0, 129)]))
+    p_seq = scn.count_pairs(j_seq)
+    warm_prm = scn.flow_params(LEVELS, ALPHA, ITERS, warm_packet=8, warm_iters=10)
+    f_cold = torch.empty((p_seq, 2, H, W), dtype=torch.float32, device=dev)
+    f_warm = torch.empty_like(f_cold)
+    ws_seq = torch.empty(max(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], prm),
+                             scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], warm_prm)), dtype=torch.uint8, device=dev)
+    seq_ms = {}
+    for name, pp, out in (("cold", prm, f_cold), ("warm", warm_prm, f_warm)):
+        scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        for _ in range(3):
+            scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
+        torch.cuda.synchronize()
+        seq_ms[name] = (time.perf_counter() - ts0) * 1e3 / 3
+    warm_epe = float(torch.sqrt(((f_warm - f_cold) ** 2).sum(dim=1)).mean())
+    del f_cold, f_warm, ws_seq
+
+    before = {"pairs": p_before, "frames_read": 2 * p_before, "ms_per_call": before_ms,
+              "pairs_per_s": p_before / (before_ms * 1e-3),
+              "note": "flow of (s, s+1) for the 100 STRIDE-24 rows, no HIST; one call, 3 reps"}
+    warm = {"pairs": p_seq, "packet": 8, "warm_iters": 10, "cold_ms_per_call": seq_ms["cold"],
+            "warm_ms_per_call": seq_ms["warm"], "speedup": seq_ms["cold"] / seq_ms["warm"],
+            "mean_epe_vs_cold_px": warm_epe, "note": "128 consecutive 1080p pairs of the stream; flow only"}
+    return before, warm
+
+
 def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_total, args):
     """Surrogate + residual-gated fallback on the same step, if trained weights exist."""
     from paper_1805_07339_amd import train as T
@@ -504,7 +557,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         "# colour source sha256(color.hip) = %s" % _source_hash(("color.hip",)),
         "# commands (from the repository root, cd /tmp && export TMPDIR=/tmp first):",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o run -- python3 bench.py --steps 1 --warmup 1 "
-        "--no-cpu-baseline --no-surrogate --calib-copy",
+        "--no-cpu-baseline --no-surrogate --no-extras --calib-copy",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o run -- python3 bench.py (same arguments)",
         "#   python3 bench.py --traffic-summary <F> <W> <bench json of the FETCH run>",
         "# copy calibration (1 GiB device copy): FETCH_SIZE %.1f KiB -> factor %.4f; WRITE_SIZE %.1f KiB -> factor %.4f"
@@ -574,6 +627,9 @@ def main():
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--tau", type=float, default=None, help="gate threshold (default: the calibrated one)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the stencil-before-sampling and warm-start legs (profiled runs: their Jacobi "
+                         "launches would follow the timed step's)")
     ap.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2",
                     help="c2: the 1080p sampled-stream step (default); c3: 64 uneven streams; c5: camera rig")
     ap.add_argument("--c3-ws-gb", type=float, default=16.0,
@@ -689,48 +745,9 @@ def main():
     conv_gbs = 4.5 * W * H * 400 * conv_n / (conv_ms * 1e-3) / 1e9
     del big, rgb
 
-    # --- stencil before sampling: flow on original neighbours (s, s+1) of the
-    # 100 STRIDE-24 rows (their successors are materialised only now)
-    for r in stride_rows:
-        if r + 1 < N_ROWS:
-            tab[r + 1] = scene.nv12(r + 1, device=dev).reshape(-1)
-    j_before = scn.Job(table, scn.Sampling.stride(24, 0, N_ROWS).before())
-    p_before = scn.count_pairs(j_before)
-    f_before = torch.empty((p_before, 2, H, W), dtype=torch.float32, device=dev)
-    ws_before = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_before], prm), dtype=torch.uint8, device=dev)
-    scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
-    torch.cuda.synchronize()
-    tb0 = time.perf_counter()
-    for _ in range(3):
-        scn.flow([j_before], prm, outs=[f_before], stream=stream, ws=ws_before)
-    torch.cuda.synchronize()
-    before_ms = (time.perf_counter() - tb0) * 1e3 / 3
-    del f_before, ws_before
-
-    # --- temporal warm start on 128 consecutive pairs (rows 0..128 of the
-    # same stream): cold pyramid (4 levels x 50 iterations) against packets of 8
-    # whose later pairs run 10 full-resolution iterations from their
-    # predecessor's flow
-    for r in range(0, 129):
-        tab[r] = scene.nv12(r, device=dev).reshape(-1)
-    j_seq = scn.Job(table, scn.Sampling.range([(0, 129)]))
-    p_seq = scn.count_pairs(j_seq)
-    warm_prm = scn.flow_params(LEVELS, ALPHA, ITERS, warm_packet=8, warm_iters=10)
-    f_cold = torch.empty((p_seq, 2, H, W), dtype=torch.float32, device=dev)
-    f_warm = torch.empty_like(f_cold)
-    ws_seq = torch.empty(max(scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], prm),
-                             scn.workspace_bytes(scn.SCN_OP_FLOW, [j_seq], warm_prm)), dtype=torch.uint8, device=dev)
-    seq_ms = {}
-    for name, pp, out in (("cold", prm, f_cold), ("warm", warm_prm, f_warm)):
-        scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
-        torch.cuda.synchronize()
-        ts0 = time.perf_counter()
-        for _ in range(3):
-            scn.flow([j_seq], pp, outs=[out], stream=stream, ws=ws_seq)
-        torch.cuda.synchronize()
-        seq_ms[name] = (time.perf_counter() - ts0) * 1e3 / 3
-    warm_epe = float(torch.sqrt(((f_warm - f_cold) ** 2).sum(dim=1)).mean())
-    del f_cold, f_warm, ws_seq
+    before_leg = warm_leg = None
+    if not args.no_extras:
+        before_leg, warm_leg = extra_legs(scn, torch, dev, tab, table, scene, stride_rows, prm, stream)
 
     surrogate = (None if args.no_surrogate else
                  surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
@@ -776,13 +793,8 @@ def main():
                  "frames_per_s": n_big * hist_n / (hist_ms * 1e-3),
                  "counter_GBps": (ctr_kv["hist_bytes_per_launch"] / (hist_ms / max(hist_n, 1) * 1e-3) / 1e9
                                   if "hist_bytes_per_launch" in ctr_kv else None)},
-        "warm_start": {"pairs": p_seq, "packet": 8, "warm_iters": 10, "cold_ms_per_call": seq_ms["cold"],
-                       "warm_ms_per_call": seq_ms["warm"], "speedup": seq_ms["cold"] / seq_ms["warm"],
-                       "mean_epe_vs_cold_px": warm_epe,
-                       "note": "128 consecutive 1080p pairs of the stream; flow only"},
-        "stencil_before_sampling": {"pairs": p_before, "frames_read": 2 * p_before, "ms_per_call": before_ms,
-                                    "pairs_per_s": p_before / (before_ms * 1e-3),
-                                    "note": "flow of (s, s+1) for the 100 STRIDE-24 rows, no HIST; one call, 3 reps"},
+        "warm_start": warm_leg,
+        "stencil_before_sampling": before_leg,
         "hist_diff": {"pairs_per_launch": n_big - 1, "avg_launch_ms": diff_ms / max(diff_n, 1),
                       "pairs_per_s": (n_big - 1) * diff_n / (diff_ms * 1e-3) if diff_ms > 0 else None,
                       "algorithmic_bytes_per_pair": 192 + 5,
