@@ -149,6 +149,12 @@ def test_warm_start_chain_matches_the_oracle():
     assert torch.equal(f, g)
     (one,) = scn.flow([job], scn.flow_params(3, 10.0, 50, warm_packet=1, warm_iters=10))
     assert torch.equal(one, plain)
+    # zero warm iterations: a later pair returns its start, its predecessor's
+    # flow, bit for bit; a packet longer than a slice restarts at the next slice
+    (z,) = scn.flow([job], scn.flow_params(3, 10.0, 50, warm_packet=100, warm_iters=0))
+    for k in range(1, 5):
+        assert torch.equal(z[k], z[0])
+    assert torch.equal(z[5], plain[5]) and torch.equal(z[6], z[5])
 
 
 def test_odd_pitch_rows_unaligned():
