@@ -4,7 +4,7 @@ gate and EPE (oracle; test infrastructure only).
 The Scanner paper runs learned models as ordinary graph operations
 (Sec. 3.1, Sec. 5.1.2 DNN) and shows, in its hyperlapse application
 (Sec. 5.2.2), a cheap per-pair cost with a conditional fallback to the full
-computation when the cheap result is not good enough.  This build's
+computation when the cheap result is not good enough.  The flow
 surrogate is that pattern applied to FLOW: a small network predicts the
 flow, a brightness-constancy residual decides per pair whether to keep it
 or to fall back to the plain Horn-Schunck solver.  The paper gives no
