@@ -237,7 +237,7 @@ constexpr int kSetupTW = 64, kSetupTH = 16;
 // exists (start flow from it).  Each thread gathers all of its halo-tile
 // samples into registers before the first LDS store, so the loads of one
 // thread overlap instead of waiting one by one.
-template <bool U8, bool COARSE, bool INIT = false>
+template <bool U8, bool COARSE, bool INIT, bool LIST>
 __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
                                                   float alpha2, int32_t tiles_x, int32_t tiles_per_pair) {
   constexpr int TW = kSetupTW + 2, NE = (kSetupTH + 2) * TW, IT = (NE + 255) / 256;
@@ -245,196 +245,210 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
   __shared__ float sI[kSetupTH + 2][kSetupTW + 2];
   __shared__ float sU[kSetupTH][kSetupTW];
   __shared__ float sV[kSetupTH][kSetupTW];
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t pr = blk / tiles_per_pair;
-  if (c.active && !c.active[pr]) return;
-  const int32_t t = blk % tiles_per_pair;
-  const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
-  const PairDesc pd = c.pairs[pr];
-  const float* init_u = INIT ? as_global(pd.init) : nullptr;
-  const float* init_v = INIT ? init_u + (int64_t)g.w * g.h : nullptr;
-  const uint8_t* y1 = nullptr;
-  const uint8_t* y2 = nullptr;
-  const float* f1 = nullptr;
-  const float* f2 = nullptr;
-  int64_t p1, p2;
-  if constexpr (U8) {
-    const FrameDesc d1 = c.frames[pd.f1], d2 = c.frames[pd.f2];
-    y1 = as_global(d1.y);
-    y2 = as_global(d2.y);
-    p1 = d1.pitch;
-    p2 = d2.pitch;
-  } else {
-    f1 = as_global(c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off);
-    f2 = as_global(c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off);
-    p1 = p2 = g.w;
-  }
-  // 32-bit byte offsets (a frame or pyramid level is far below 4 GiB)
-  const uint32_t q1 = (uint32_t)p1, q2 = (uint32_t)p2;
-  // rows < 2^15 and pitches <= 2^20 (checked on the host): 24-bit products
-  auto at1 = [&](int32_t xx, int32_t yy) -> float {
-    if constexpr (U8) return (float)ldg(y1, __umul24((uint32_t)yy, q1) + (uint32_t)xx);
-    else return ldg(f1, 4u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
-  };
-  // Warped I2 at (X, Y) = (xi + xf, yi + yf), X given as integer + fraction
-  // (exact far from the origin), clamped bilinear: outside [0, w-2] the x
-  // fraction is 0 at the clamped column (likewise in y).  The two columns of
-  // a row are read by one load (2 bytes at level 0, 8 bytes above; unaligned
-  // global loads are allowed) at xs = clamp(xi, 0, w - 2); past the right
-  // edge the clamped sample is the second element with weight 1, which is
-  // the same value as the clamped column with weight 0.
-  auto warp_sample = [&](int32_t xi, float xf, int32_t yi, float yf) -> float {
-    int32_t xs;
-    float fx;
-    if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= g.w - 1) { xs = g.w - 2; fx = 1.f; } else { xs = xi; fx = xf; }
-    const bool iny = (uint32_t)yi < (uint32_t)(g.h - 1);
-    const int32_t y0 = clampi(yi, 0, g.h - 1), y1 = y0 + (iny ? 1 : 0);
-    const float fy = iny ? yf : 0.f;
-    float a0, b0, a1, b1;
-    if constexpr (U8) {
-      const uint32_t w0 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y0, q2) + (uint32_t)xs);
-      const uint32_t w1 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y1, q2) + (uint32_t)xs);
-      a0 = (float)(w0 & 0xFFu);
-      b0 = (float)(w0 >> 8);
-      a1 = (float)(w1 & 0xFFu);
-      b1 = (float)(w1 >> 8);
+  // A workgroup takes tile `unit` = its index; with an active-pair list (a
+  // masked solve) the units index list slots and the grid, sized for a
+  // fraction of the pairs, strides over them until the list is exhausted.
+  // (units stay below 2^31: the host bounds tiles x pairs)
+  for (uint32_t unit = xcd_block(blockIdx.x, gridDim.x);; unit += gridDim.x) {
+    int64_t pr;
+    const uint32_t slot = unit / (uint32_t)tiles_per_pair;
+    if constexpr (LIST) {
+      if ((int64_t)slot >= *c.act_count) return;
+      pr = c.act_list[slot];
     } else {
-      typedef float f2v __attribute__((ext_vector_type(2)));
-      const f2v r0 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y0, q2) + (uint32_t)xs));
-      const f2v r1 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y1, q2) + (uint32_t)xs));
-      a0 = r0.x;
-      b0 = r0.y;
-      a1 = r1.x;
-      b1 = r1.y;
+      pr = slot;
+      if (c.active && !c.active[pr]) return;
     }
-    const float top = (1.f - fx) * a0 + fx * b0;
-    const float bot = (1.f - fx) * a1 + fx * b1;
-    return (1.f - fy) * top + fy * bot;
-  };
-  // Start flow = 2 * bilinear(coarse flow, x/2, y/2), separably: the
-  // horizontal interpolation of the coarse rows under the tile ((oy-1)/2 ..
-  // (oy+16)/2 + 1, at most 11, clamped to the coarse level) at each of the
-  // tile's 66 halo columns goes to LDS once; each halo pixel then combines
-  // two of those rows.  Same operands and operation order as the plain
-  // bilinear formula, so the values are identical.
-  constexpr int CH = kSetupTH / 2 + 3;
-  __shared__ float sHU[COARSE ? CH : 1][COARSE ? TW : 1];
-  __shared__ float sHV[COARSE ? CH : 1][COARSE ? TW : 1];
-  int32_t cy_lo = 0;
-  if constexpr (COARSE) {
-    const float* cu = uv_buf(c, pr, coarse_code, g.n0);
-    const float* cv = cu + (int64_t)g.cw * g.ch;
-    cy_lo = min(max(oy - 1, 0) >> 1, g.ch - 1);
-    constexpr int NH = CH * TW, ITH = (NH + 255) / 256;
-    const uint32_t cw4 = 4u * (uint32_t)g.cw;
-    float ha[ITH], hb[ITH], hc[ITH], hd[ITH], hf[ITH];
-#pragma unroll
-    for (int i = 0; i < ITH; ++i) {
-      const int e = min((int)threadIdx.x + i * 256, NH - 1);
-      const int32_t yy = min(cy_lo + e / TW, g.ch - 1);
-      const int32_t x = clampi(ox + e % TW - 1, 0, g.w - 1), xi = x >> 1;
-      int32_t x0;
-      if (xi >= g.cw - 1) { x0 = g.cw - 1; hf[i] = 0.f; }
-      else { x0 = xi; hf[i] = (x & 1) ? 0.5f : 0.f; }
-      const int32_t x1 = min(x0 + 1, g.cw - 1);
-      const uint32_t r = __umul24((uint32_t)yy, cw4);
-      ha[i] = ldg(cu, r + 4u * (uint32_t)x0);
-      hb[i] = ldg(cu, r + 4u * (uint32_t)x1);
-      hc[i] = ldg(cv, r + 4u * (uint32_t)x0);
-      hd[i] = ldg(cv, r + 4u * (uint32_t)x1);
+    const int32_t t = (int32_t)(unit % (uint32_t)tiles_per_pair);
+    const int32_t ox = (t % tiles_x) * kSetupTW, oy = (t / tiles_x) * kSetupTH;
+    const PairDesc pd = c.pairs[pr];
+    const float* init_u = INIT ? as_global(pd.init) : nullptr;
+    const float* init_v = INIT ? init_u + (int64_t)g.w * g.h : nullptr;
+    const uint8_t* y1 = nullptr;
+    const uint8_t* y2 = nullptr;
+    const float* f1 = nullptr;
+    const float* f2 = nullptr;
+    int64_t p1, p2;
+    if constexpr (U8) {
+      const FrameDesc d1 = c.frames[pd.f1], d2 = c.frames[pd.f2];
+      y1 = as_global(d1.y);
+      y2 = as_global(d2.y);
+      p1 = d1.pitch;
+      p2 = d2.pitch;
+    } else {
+      f1 = as_global(c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off);
+      f2 = as_global(c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off);
+      p1 = p2 = g.w;
     }
-#pragma unroll
-    for (int i = 0; i < ITH; ++i) {
+    // 32-bit byte offsets (a frame or pyramid level is far below 4 GiB)
+    const uint32_t q1 = (uint32_t)p1, q2 = (uint32_t)p2;
+    // rows < 2^15 and pitches <= 2^20 (checked on the host): 24-bit products
+    auto at1 = [&](int32_t xx, int32_t yy) -> float {
+      if constexpr (U8) return (float)ldg(y1, __umul24((uint32_t)yy, q1) + (uint32_t)xx);
+      else return ldg(f1, 4u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
+    };
+    // Warped I2 at (X, Y) = (xi + xf, yi + yf), X given as integer + fraction
+    // (exact far from the origin), clamped bilinear: outside [0, w-2] the x
+    // fraction is 0 at the clamped column (likewise in y).  The two columns of
+    // a row are read by one load (2 bytes at level 0, 8 bytes above; unaligned
+    // global loads are allowed) at xs = clamp(xi, 0, w - 2); past the right
+    // edge the clamped sample is the second element with weight 1, which is
+    // the same value as the clamped column with weight 0.
+    auto warp_sample = [&](int32_t xi, float xf, int32_t yi, float yf) -> float {
+      int32_t xs;
+      float fx;
+      if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= g.w - 1) { xs = g.w - 2; fx = 1.f; } else { xs = xi; fx = xf; }
+      const bool iny = (uint32_t)yi < (uint32_t)(g.h - 1);
+      const int32_t y0 = clampi(yi, 0, g.h - 1), y1 = y0 + (iny ? 1 : 0);
+      const float fy = iny ? yf : 0.f;
+      float a0, b0, a1, b1;
+      if constexpr (U8) {
+        const uint32_t w0 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y0, q2) + (uint32_t)xs);
+        const uint32_t w1 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y1, q2) + (uint32_t)xs);
+        a0 = (float)(w0 & 0xFFu);
+        b0 = (float)(w0 >> 8);
+        a1 = (float)(w1 & 0xFFu);
+        b1 = (float)(w1 >> 8);
+      } else {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        const f2v r0 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y0, q2) + (uint32_t)xs));
+        const f2v r1 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y1, q2) + (uint32_t)xs));
+        a0 = r0.x;
+        b0 = r0.y;
+        a1 = r1.x;
+        b1 = r1.y;
+      }
+      const float top = (1.f - fx) * a0 + fx * b0;
+      const float bot = (1.f - fx) * a1 + fx * b1;
+      return (1.f - fy) * top + fy * bot;
+    };
+    // Start flow = 2 * bilinear(coarse flow, x/2, y/2), separably: the
+    // horizontal interpolation of the coarse rows under the tile ((oy-1)/2 ..
+    // (oy+16)/2 + 1, at most 11, clamped to the coarse level) at each of the
+    // tile's 66 halo columns goes to LDS once; each halo pixel then combines
+    // two of those rows.  Same operands and operation order as the plain
+    // bilinear formula, so the values are identical.
+    constexpr int CH = kSetupTH / 2 + 3;
+    __shared__ float sHU[COARSE ? CH : 1][COARSE ? TW : 1];
+    __shared__ float sHV[COARSE ? CH : 1][COARSE ? TW : 1];
+    int32_t cy_lo = 0;
+    if constexpr (COARSE) {
+      const float* cu = uv_buf(c, pr, coarse_code, g.n0);
+      const float* cv = cu + (int64_t)g.cw * g.ch;
+      cy_lo = min(max(oy - 1, 0) >> 1, g.ch - 1);
+      constexpr int NH = CH * TW, ITH = (NH + 255) / 256;
+      const uint32_t cw4 = 4u * (uint32_t)g.cw;
+      float ha[ITH], hb[ITH], hc[ITH], hd[ITH], hf[ITH];
+  #pragma unroll
+      for (int i = 0; i < ITH; ++i) {
+        const int e = min((int)threadIdx.x + i * 256, NH - 1);
+        const int32_t yy = min(cy_lo + e / TW, g.ch - 1);
+        const int32_t x = clampi(ox + e % TW - 1, 0, g.w - 1), xi = x >> 1;
+        int32_t x0;
+        if (xi >= g.cw - 1) { x0 = g.cw - 1; hf[i] = 0.f; }
+        else { x0 = xi; hf[i] = (x & 1) ? 0.5f : 0.f; }
+        const int32_t x1 = min(x0 + 1, g.cw - 1);
+        const uint32_t r = __umul24((uint32_t)yy, cw4);
+        ha[i] = ldg(cu, r + 4u * (uint32_t)x0);
+        hb[i] = ldg(cu, r + 4u * (uint32_t)x1);
+        hc[i] = ldg(cv, r + 4u * (uint32_t)x0);
+        hd[i] = ldg(cv, r + 4u * (uint32_t)x1);
+      }
+  #pragma unroll
+      for (int i = 0; i < ITH; ++i) {
+        const int e = threadIdx.x + i * 256;
+        if (e < NH) {
+          const float fx = hf[i];
+          sHU[e / TW][e % TW] = (1.f - fx) * ha[i] + fx * hb[i];
+          sHV[e / TW][e % TW] = (1.f - fx) * hc[i] + fx * hd[i];
+        }
+      }
+      __syncthreads();
+    }
+    float rT[IT], rI[IT], rU[IT], rV[IT];
+    // halo element e = tid + 256 i at (ty, tx) = (e / TW, e % TW), advanced
+    // incrementally (256 = 3 TW + 58); elements past the tile repeat the last
+    int hty = (int)threadIdx.x / TW, htx = (int)threadIdx.x % TW;
+  #pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      if (i > 0) {
+        htx += 256 % TW;
+        hty += 256 / TW;
+        if (htx >= TW) { htx -= TW; ++hty; }
+      }
+      const bool past = hty >= kSetupTH + 2;
+      const int ty = past ? kSetupTH + 1 : hty, tx = past ? TW - 1 : htx;
+      const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
+      float u0 = 0.f, v0 = 0.f;
+      if constexpr (INIT) {
+        // warm start: the predecessor pair's full-resolution flow
+        const uint32_t o = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
+        u0 = ldg(init_u, o);
+        v0 = ldg(init_v, o);
+      }
+      if constexpr (COARSE) {
+        const int32_t yi = y >> 1;
+        int32_t y0;
+        float fy;
+        if (yi >= g.ch - 1) { y0 = g.ch - 1; fy = 0.f; }
+        else { y0 = yi; fy = (y & 1) ? 0.5f : 0.f; }
+        const int r0 = y0 - cy_lo, r1 = min(y0 + 1, g.ch - 1) - cy_lo;
+        u0 = 2.f * ((1.f - fy) * sHU[r0][tx] + fy * sHU[r1][tx]);
+        v0 = 2.f * ((1.f - fy) * sHV[r0][tx] + fy * sHV[r1][tx]);
+      }
+      const float fu = floorf(u0), fv = floorf(v0);
+      rT[i] = warp_sample(x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
+      rI[i] = at1(x, y);
+      rU[i] = u0;
+      rV[i] = v0;
+    }
+  #pragma unroll
+    for (int i = 0; i < IT; ++i) {
       const int e = threadIdx.x + i * 256;
-      if (e < NH) {
-        const float fx = hf[i];
-        sHU[e / TW][e % TW] = (1.f - fx) * ha[i] + fx * hb[i];
-        sHV[e / TW][e % TW] = (1.f - fx) * hc[i] + fx * hd[i];
+      if (e >= NE) break;
+      const int ty = e / TW, tx = e % TW;
+      sT[ty][tx] = rT[i];
+      sI[ty][tx] = rI[i];
+      const int iy = ty - 1, ix = tx - 1;
+      if (iy >= 0 && iy < kSetupTH && ix >= 0 && ix < kSetupTW) {
+        sU[iy][ix] = rU[i];
+        sV[iy][ix] = rV[i];
       }
     }
     __syncthreads();
-  }
-  float rT[IT], rI[IT], rU[IT], rV[IT];
-  // halo element e = tid + 256 i at (ty, tx) = (e / TW, e % TW), advanced
-  // incrementally (256 = 3 TW + 58); elements past the tile repeat the last
-  int hty = (int)threadIdx.x / TW, htx = (int)threadIdx.x % TW;
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    if (i > 0) {
-      htx += 256 % TW;
-      hty += 256 / TW;
-      if (htx >= TW) { htx -= TW; ++hty; }
+    const int64_t n = (int64_t)g.w * g.h;
+    float* pa = plane(c, pr, kPlaneA, g.n0);
+    float* pb = plane(c, pr, kPlaneB, g.n0);
+    float* pc = plane(c, pr, kPlaneC, g.n0);
+    float* dst = uv_buf(c, pr, dst_code, g.n0);
+    for (int e = threadIdx.x; e < kSetupTH * kSetupTW; e += 256) {
+      const int ly = e / kSetupTW, lx = e % kSetupTW;
+      const int32_t x = ox + lx, y = oy + ly;
+      if (x >= g.w || y >= g.h) continue;
+      const int hx = lx + 1, hy = ly + 1;
+      // clamp-to-edge neighbours: the halo holds the clamped pixels, and at the
+      // image's own border the neighbour index is clamped onto the pixel itself
+      const int xl = (x > 0) ? hx - 1 : hx, xr = (x < g.w - 1) ? hx + 1 : hx;
+      const int yu = (y > 0) ? hy - 1 : hy, yd = (y < g.h - 1) ? hy + 1 : hy;
+      const float u0 = sU[ly][lx], v0 = sV[ly][lx];
+      // Ix = (central difference of I1 + that of T) / 2 with each difference
+      // halved: the two power-of-two scalings are folded into one factor 1/4
+      // (exact: scaling by 2^-k commutes with rounding for these magnitudes)
+      const float Ix = ((sI[hy][xr] - sI[hy][xl]) + (sT[hy][xr] - sT[hy][xl])) * 0.25f;
+      const float Iy = ((sI[yd][hx] - sI[yu][hx]) + (sT[yd][hx] - sT[yu][hx])) * 0.25f;
+      const float It = sT[hy][hx] - sI[hy][hx];
+      const float Itp = It - Ix * u0 - Iy * v0;
+      const float den = alpha2 + Ix * Ix + Iy * Iy;
+      const float r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
+      const uint32_t p4 = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
+      stg(pa, p4, Ix * r);
+      stg(pb, p4, Iy * r);
+      stg(pc, p4, Itp * r);
+      stg(dst, p4, u0);
+      stg(dst, p4 + 4u * (uint32_t)n, v0);
     }
-    const bool past = hty >= kSetupTH + 2;
-    const int ty = past ? kSetupTH + 1 : hty, tx = past ? TW - 1 : htx;
-    const int32_t x = clampi(ox + tx - 1, 0, g.w - 1), y = clampi(oy + ty - 1, 0, g.h - 1);
-    float u0 = 0.f, v0 = 0.f;
-    if constexpr (INIT) {
-      // warm start: the predecessor pair's full-resolution flow
-      const uint32_t o = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
-      u0 = ldg(init_u, o);
-      v0 = ldg(init_v, o);
-    }
-    if constexpr (COARSE) {
-      const int32_t yi = y >> 1;
-      int32_t y0;
-      float fy;
-      if (yi >= g.ch - 1) { y0 = g.ch - 1; fy = 0.f; }
-      else { y0 = yi; fy = (y & 1) ? 0.5f : 0.f; }
-      const int r0 = y0 - cy_lo, r1 = min(y0 + 1, g.ch - 1) - cy_lo;
-      u0 = 2.f * ((1.f - fy) * sHU[r0][tx] + fy * sHU[r1][tx]);
-      v0 = 2.f * ((1.f - fy) * sHV[r0][tx] + fy * sHV[r1][tx]);
-    }
-    const float fu = floorf(u0), fv = floorf(v0);
-    rT[i] = warp_sample(x + (int32_t)fu, u0 - fu, y + (int32_t)fv, v0 - fv);
-    rI[i] = at1(x, y);
-    rU[i] = u0;
-    rV[i] = v0;
-  }
-#pragma unroll
-  for (int i = 0; i < IT; ++i) {
-    const int e = threadIdx.x + i * 256;
-    if (e >= NE) break;
-    const int ty = e / TW, tx = e % TW;
-    sT[ty][tx] = rT[i];
-    sI[ty][tx] = rI[i];
-    const int iy = ty - 1, ix = tx - 1;
-    if (iy >= 0 && iy < kSetupTH && ix >= 0 && ix < kSetupTW) {
-      sU[iy][ix] = rU[i];
-      sV[iy][ix] = rV[i];
-    }
-  }
-  __syncthreads();
-  const int64_t n = (int64_t)g.w * g.h;
-  float* pa = plane(c, pr, kPlaneA, g.n0);
-  float* pb = plane(c, pr, kPlaneB, g.n0);
-  float* pc = plane(c, pr, kPlaneC, g.n0);
-  float* dst = uv_buf(c, pr, dst_code, g.n0);
-  for (int e = threadIdx.x; e < kSetupTH * kSetupTW; e += 256) {
-    const int ly = e / kSetupTW, lx = e % kSetupTW;
-    const int32_t x = ox + lx, y = oy + ly;
-    if (x >= g.w || y >= g.h) continue;
-    const int hx = lx + 1, hy = ly + 1;
-    // clamp-to-edge neighbours: the halo holds the clamped pixels, and at the
-    // image's own border the neighbour index is clamped onto the pixel itself
-    const int xl = (x > 0) ? hx - 1 : hx, xr = (x < g.w - 1) ? hx + 1 : hx;
-    const int yu = (y > 0) ? hy - 1 : hy, yd = (y < g.h - 1) ? hy + 1 : hy;
-    const float u0 = sU[ly][lx], v0 = sV[ly][lx];
-    // Ix = (central difference of I1 + that of T) / 2 with each difference
-    // halved: the two power-of-two scalings are folded into one factor 1/4
-    // (exact: scaling by 2^-k commutes with rounding for these magnitudes)
-    const float Ix = ((sI[hy][xr] - sI[hy][xl]) + (sT[hy][xr] - sT[hy][xl])) * 0.25f;
-    const float Iy = ((sI[yd][hx] - sI[yu][hx]) + (sT[yd][hx] - sT[yu][hx])) * 0.25f;
-    const float It = sT[hy][hx] - sI[hy][hx];
-    const float Itp = It - Ix * u0 - Iy * v0;
-    const float den = alpha2 + Ix * Ix + Iy * Iy;
-    const float r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
-    const uint32_t p4 = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
-    stg(pa, p4, Ix * r);
-    stg(pb, p4, Iy * r);
-    stg(pc, p4, Itp * r);
-    stg(dst, p4, u0);
-    stg(dst, p4 + 4u * (uint32_t)n, v0);
+    if constexpr (!LIST) return;  // one tile per workgroup without a list
+    __syncthreads();              // the next tile reuses the LDS arrays
   }
 }
 
@@ -1041,23 +1055,27 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       const int64_t tpp = (int64_t)tiles_x * tiles_y;
       if (tpp * ch.n_pairs > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
       KernelTimer timer("hs_setup", s);
-      const dim3 grid((unsigned)(tpp * ch.n_pairs));
+      // with an active-pair list the grid covers about one pair in eight and
+      // the workgroups stride over the list (as the streaming Jacobi does)
+      const int64_t n_grid = c.act_list ? std::max<int64_t>(1, (ch.n_pairs + 7) / 8) : ch.n_pairs;
+      const dim3 grid((unsigned)(tpp * n_grid));
       const bool u8 = g.level == 0, co = g.has_coarse != 0;
-      if (warm)
-        hipLaunchKernelGGL((k_hs_setup<true, false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
-                           tiles_x, (int32_t)tpp);
-      else if (u8 && co)
-        hipLaunchKernelGGL((k_hs_setup<true, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
-                           tiles_x, (int32_t)tpp);
-      else if (u8)
-        hipLaunchKernelGGL((k_hs_setup<true, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
-                           tiles_x, (int32_t)tpp);
-      else if (co)
-        hipLaunchKernelGGL((k_hs_setup<false, true>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
-                           tiles_x, (int32_t)tpp);
-      else
-        hipLaunchKernelGGL((k_hs_setup<false, false>), grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2,
-                           tiles_x, (int32_t)tpp);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x, (int32_t)tpp);
+      };
+      if (c.act_list) {
+        if (warm) go(k_hs_setup<true, false, true, true>);
+        else if (u8 && co) go(k_hs_setup<true, true, false, true>);
+        else if (u8) go(k_hs_setup<true, false, false, true>);
+        else if (co) go(k_hs_setup<false, true, false, true>);
+        else go(k_hs_setup<false, false, false, true>);
+      } else {
+        if (warm) go(k_hs_setup<true, false, true, false>);
+        else if (u8 && co) go(k_hs_setup<true, true, false, false>);
+        else if (u8) go(k_hs_setup<true, false, false, false>);
+        else if (co) go(k_hs_setup<false, true, false, false>);
+        else go(k_hs_setup<false, false, false, false>);
+      }
     }
     SCN_LAUNCHED("setup launch");
     int32_t cur = start_dst;
