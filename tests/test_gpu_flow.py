@@ -241,10 +241,12 @@ def test_jacobi_schedules_are_bitwise_identical(w, h, levels):
     assert torch.equal(f, ref)
 
 
-def test_graph_capture_replays_match_eager():
+@pytest.mark.parametrize("warm", [0, 2])
+def test_graph_capture_replays_match_eager(warm):
     """After one eager call (plan upload, tuning), the flow and HIST calls of an
     uneven multi-job batch are captured into a HIP graph; every replay, with
-    eager work in between, reproduces the eager result bit for bit."""
+    eager work in between, reproduces the eager result bit for bit (also with
+    the warm start, whose later pairs read their predecessors' outputs)."""
     need_gpu()
     fa, _ = c1_frames(n=4, w=160, h=120, seed=21)
     fb, _ = c1_frames(n=4, w=96, h=64, seed=22)
@@ -252,7 +254,7 @@ def test_graph_capture_replays_match_eager():
     tb = table_from_frames(fb, 4, [0, 1, 2, 3], 96, 64)
     ja = scn.Job(scn.Table.from_tensor(ta, 160, 120), scn.Sampling.stride(1, 0, 4))
     jb = scn.Job(scn.Table.from_tensor(tb, 96, 64), scn.Sampling.range([(0, 4)]))
-    p = scn.flow_params(levels=3)
+    p = scn.flow_params(levels=3, warm_packet=warm, warm_iters=5)
     outs = [torch.empty((3, 2, 120, 160), device="cuda"), torch.empty((3, 2, 64, 96), device="cuda")]
     hist = torch.empty((4, 3, 16), dtype=torch.int32, device="cuda")
     ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, [ja, jb], p), dtype=torch.uint8, device="cuda")
