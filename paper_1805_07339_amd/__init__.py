@@ -200,7 +200,8 @@ class Sampling:
 
     def before(self) -> "Sampling":
         """The same rows with the flow stencil applied before sampling: pairs
-        (s, s+1) of original rows for each sampled row s."""
+        (s, s+1) of original rows for each sampled row s.  A Job copies its
+        sampling when it is built, so call this before building the Job."""
         self.stencil = SCN_STENCIL_BEFORE
         return self
 
