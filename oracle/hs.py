@@ -37,7 +37,13 @@ right sign; transposing both frames swaps u and v; at one level a horizontal
 mirror negates u; the Jacobi fixed point equals a sparse direct solve of the
 Horn-Schunck normal equations; the blur of an impulse is the binomial
 outer product; an integer warp is an exact shift; upsampling a constant c
-gives 2c.  Parity pinned.
+gives 2c.  The border and coordinate conventions are pinned by values worked
+out by hand: the clamped blur of a corner impulse and of a ramp, the even
+samples of a clamped ramp, half one-sided differences of x^2 + 5 at both
+ends, the upsampling of a coarse ramp (coarse sample k at fine 2k), and
+bilinear sampling of a function in span{1, x, y, xy} (exact inside,
+clamped outside).  A mutation test plants a mistake at each of these places
+and checks that a pin fails.  Parity pinned.
 """
 from __future__ import annotations
 

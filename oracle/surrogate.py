@@ -35,7 +35,8 @@ Pins (tests): forward of each layer against torch.nn.functional.conv2d in
 FP64 on the same BF16-rounded inputs; backward against torch FP64 autograd
 and against central finite differences; Adam on a linear objective against
 its closed form; BF16 rounding against torch's bfloat16 conversion; the
-upsampling operator against its transpose (adjoint identity).  The trained
+upsampling operator against its transpose (adjoint identity); EPE against
+closed forms (constant offsets, half-image offsets).  The trained
 network's quality is parity unpinned (only the EPE measurement judges it).
 """
 from __future__ import annotations

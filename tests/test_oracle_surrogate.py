@@ -168,3 +168,20 @@ def test_residual_gate_statistic():
     assert r_full < r_zero
     from oracle.hs import warp
     assert np.array_equal(warp(y2.astype(float), flow[0], flow[1])[:, :-3], y1[:, :-3].astype(float))
+
+
+def test_epe_closed_forms():
+    """EPE (per-pixel endpoint distance, mean over pixels): zero against
+    itself; a constant (3, 4) offset gives exactly 5; half the pixels off by
+    (0, 2) and half exact gives 1 (catches a squared, summed or per-component
+    error measure)."""
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=(2, 6, 8))
+    assert S.epe(f, f) == 0.0
+    off = f.copy()
+    off[0] += 3.0
+    off[1] += 4.0
+    assert abs(S.epe(off, f) - 5.0) < 1e-12
+    half = f.copy()
+    half[1, :3] += 2.0
+    assert abs(S.epe(half, f) - 1.0) < 1e-12
