@@ -101,7 +101,8 @@ def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray, stride: int) -> np.ndar
     for ky in range(3):
         for kx in range(3):
             patch = xp[:, ky:ky + stride * (Ho - 1) + 1:stride, kx:kx + stride * (Wo - 1) + 1:stride]
-            out += np.einsum("oc,chw->ohw", w[:, :, ky, kx], patch)
+            # the channel contraction of one tap, as a library matrix product
+            out += np.tensordot(w[:, :, ky, kx], patch, axes=([1], [0]))
     return out
 
 
@@ -116,8 +117,8 @@ def conv3x3_backward(x: np.ndarray, w: np.ndarray, stride: int, gout: np.ndarray
         for kx in range(3):
             sl = (slice(None), slice(ky, ky + stride * (Ho - 1) + 1, stride),
                   slice(kx, kx + stride * (Wo - 1) + 1, stride))
-            gw[:, :, ky, kx] = np.einsum("ohw,chw->oc", gout, xp[sl])
-            gxp[sl] += np.einsum("oc,ohw->chw", w[:, :, ky, kx], gout)
+            gw[:, :, ky, kx] = np.tensordot(gout, xp[sl], axes=([1, 2], [1, 2]))
+            gxp[sl] += np.tensordot(w[:, :, ky, kx], gout, axes=([0], [0]))
     gb = gout.sum(axis=(1, 2))
     return gxp[:, 1:H + 1, 1:W + 1], gw, gb
 
@@ -191,13 +192,14 @@ def flow_full(half: np.ndarray) -> np.ndarray:
     _, h, w = half.shape
     My = upsample_flow_matrix_1d(h)
     Mx = upsample_flow_matrix_1d(w)
-    return 2.0 * np.einsum("yh,chw,xw->cyx", My, half, Mx)
+    # separable: rows with My, columns with Mx (library matrix products)
+    return 2.0 * np.stack([My @ half[c] @ Mx.T for c in range(half.shape[0])])
 
 
 def flow_full_adjoint(g_full: np.ndarray, h: int, w: int) -> np.ndarray:
     My = upsample_flow_matrix_1d(h)
     Mx = upsample_flow_matrix_1d(w)
-    return 2.0 * np.einsum("yh,cyx,xw->chw", My, g_full, Mx)
+    return 2.0 * np.stack([My.T @ g_full[c] @ Mx for c in range(g_full.shape[0])])
 
 
 def charbonnier_loss(full: np.ndarray, target: np.ndarray):
