@@ -34,12 +34,21 @@
  *   - Empty samplings (no rows, or no pairs for flow) return SCN_OK and
  *     enqueue nothing.
  *   - The caller owns every buffer.  `ws` is scratch device memory of
- *     `ws_bytes` bytes (size it with scn_workspace_bytes); its contents
- *     persist between calls.  The library uploads a small plan (row and pair
- *     tables) to the start of `ws` and skips the upload when the same plan
- *     was last uploaded to the same `ws`; a caller that writes into `ws`
- *     itself must call scn_ws_forget(ws) first.  Calls that share one `ws`
- *     must be ordered on one stream.
+ *     `ws_bytes` bytes (size it with scn_workspace_bytes).  Every call made
+ *     outside graph capture copies a small plan (row and pair tables) from
+ *     host memory to the start of `ws`, ordered on its stream, so `ws` may
+ *     hold anything between calls.  Calls that share one `ws` must be
+ *     ordered on one stream (they overwrite each other's scratch).
+ *   - HIP graph capture: a call made on a capturing stream records kernel
+ *     launches only, no host-to-device copy.  It is accepted only if the last
+ *     plan uploaded to the same `ws` (by an eager call) is exactly its own
+ *     plan; otherwise it returns SCN_EINVAL with nothing recorded ("make the
+ *     same call eagerly first").  The graph's kernels then read the plan
+ *     that the workspace holds when the graph is replayed: between replays,
+ *     do not run calls with a different plan on that `ws`, and do not write
+ *     into its head, or re-run the eager call before replaying.
+ *     scn_ws_forget(ws) drops the record of the last upload to `ws` (a later
+ *     capture on it is refused until an eager call uploads again).
  */
 #ifndef SCN_H
 #define SCN_H
@@ -69,12 +78,19 @@ typedef enum {
  * 2^20; frame_bytes >= pitch * height * 3 / 2, and that Y + UV extent is at
  * most 2 GiB (kernels address a frame with 32-bit offsets).  Tables outside
  * these limits are refused with SCN_EUNSUPPORTED.
- * Only the rows a call samples are read, so only those rows need to be backed
- * by memory (a table may be a view of which a window of rows is resident). */
+ * Only the rows a call reads are touched (its sampled rows, plus row s+1 of
+ * each sampled row s with SCN_STENCIL_BEFORE), so only those rows need to be
+ * backed by memory: a table may be a view of which a window of rows is
+ * resident.  backed_count > 0 declares that only rows [backed_first,
+ * backed_first + backed_count) are backed; every call then refuses with
+ * SCN_EINVAL a job that would read another row.  backed_count == 0 (a
+ * zero-initialised field) declares every row backed.  backed_first >= 0 and
+ * backed_first + backed_count <= n_frames, else SCN_EINVAL. */
 typedef struct {
   const uint8_t* frames; /* device */
   int32_t width, height, pitch, reserved;
   int64_t frame_bytes, n_frames;
+  int64_t backed_first, backed_count;
 } scn_table;
 
 typedef enum { SCN_STRIDE = 0, SCN_GATHER = 1, SCN_RANGE = 2 } scn_sample_kind;
@@ -291,7 +307,8 @@ scn_status scn_timing_enable(int32_t enable, int32_t max_launches);
 scn_status scn_timing_reset(void);
 scn_status scn_timing_read(const char* kernel, double* total_ms, int64_t* launches);
 
-/* Forget any plan cached for `ws` (call after writing into ws yourself). */
+/* Drop the record of the last plan uploaded to `ws` (for example before the
+ * memory is freed; a capture on `ws` is then refused until an eager call). */
 void scn_ws_forget(const void* ws);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */

@@ -39,7 +39,7 @@ class ScnError(RuntimeError):
 class CTable(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("pitch", ctypes.c_int32), ("reserved", ctypes.c_int32), ("frame_bytes", ctypes.c_int64),
-                ("n_frames", ctypes.c_int64)]
+                ("n_frames", ctypes.c_int64), ("backed_first", ctypes.c_int64), ("backed_count", ctypes.c_int64)]
 
 
 class CSampling(ctypes.Structure):
@@ -159,19 +159,23 @@ class Table:
     frame_bytes: int
     n_frames: int
     row0: int = 0  # table row held by frames[0] (window views)
+    backed: int = 0  # rows row0 .. row0 + backed - 1 are backed (0: every row)
 
     @staticmethod
     def window(rows: torch.Tensor, first_row: int, n_frames: int, width: int, height: int,
                pitch: Optional[int] = None) -> "Table":
         """A table of n_frames rows of which only rows first_row .. first_row +
         len(rows) - 1 are backed by memory (rows[i] holds row first_row + i).
-        Only sampled rows are ever read, so a job may use such a view as long as
-        its sampling stays inside the backed rows (Sec. 4.2: frames that no
-        output needs are never materialised)."""
+        Only the rows a job reads are touched, so a job may use such a view as
+        long as those rows are backed (Sec. 4.2: frames that no output needs
+        are never materialised); the library refuses jobs that read outside
+        the window."""
         t = Table.from_tensor(rows, width, height, pitch)
         if first_row < 0 or first_row + t.n_frames > n_frames:
             raise ValueError("window rows fall outside the table")
-        t.row0, t.n_frames = first_row, n_frames
+        if t.n_frames == 0:
+            raise ValueError("a window needs at least one backed row")
+        t.row0, t.backed, t.n_frames = first_row, t.n_frames, n_frames
         return t
 
     @staticmethod
@@ -185,7 +189,7 @@ class Table:
 
     def c(self) -> CTable:
         return CTable(self.frames.data_ptr() - self.row0 * self.frame_bytes, self.width, self.height, self.pitch, 0,
-                      self.frame_bytes, self.n_frames)
+                      self.frame_bytes, self.n_frames, self.row0 if self.backed else 0, self.backed)
 
 
 class Sampling:

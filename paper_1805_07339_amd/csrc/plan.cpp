@@ -24,6 +24,11 @@ scn_status check_table(const scn_table* t) {
   const int64_t need = (int64_t)t->pitch * (t->height + t->height / 2);
   if (t->frame_bytes < need) { set_error("table frame_bytes < pitch * height * 3/2"); return SCN_EINVAL; }
   if (t->n_frames > 0 && !t->frames) { set_error("table frames pointer is NULL"); return SCN_EINVAL; }
+  if (t->backed_first < 0 || t->backed_count < 0 ||
+      (t->backed_count > 0 && t->backed_first > t->n_frames - t->backed_count)) {
+    set_error("table backed rows must lie inside [0, n_frames)");
+    return SCN_EINVAL;
+  }
   if (t->width > (1 << 15) || t->height > (1 << 15)) {
     set_error("frame dimensions above 32768 are not supported");
     return SCN_EUNSUPPORTED;
@@ -54,13 +59,18 @@ scn_status resolve(const scn_job* job, std::vector<Slice>* out) {
         set_error("stride needs 0 <= start <= stop <= n_frames");
         return SCN_EINVAL;
       }
+      // count first (no overflow: 0 <= start <= stop), rows as start + i * step
+      const int64_t count = s.stop > s.start ? (s.stop - s.start - 1) / s.step + 1 : 0;
+      if (count > kMaxRows) { set_error("sampling selects more than 2^31 - 1 rows"); return SCN_EUNSUPPORTED; }
       Slice sl;
-      for (int64_t r = s.start; r < s.stop; r += s.step) sl.rows.push_back(r);
+      sl.rows.reserve((size_t)count);
+      for (int64_t i = 0; i < count; ++i) sl.rows.push_back(s.start + i * s.step);
       out->push_back(std::move(sl));
       return SCN_OK;
     }
     case SCN_GATHER: {
       if (s.n < 0 || (s.n > 0 && !s.idx)) { set_error("gather list is NULL or n < 0"); return SCN_EINVAL; }
+      if (s.n > kMaxRows) { set_error("sampling selects more than 2^31 - 1 rows"); return SCN_EUNSUPPORTED; }
       Slice sl;
       sl.rows.reserve((size_t)s.n);
       for (int64_t i = 0; i < s.n; ++i) {
@@ -74,17 +84,25 @@ scn_status resolve(const scn_job* job, std::vector<Slice>* out) {
     }
     case SCN_RANGE: {
       if (s.n < 0 || (s.n > 0 && !s.idx)) { set_error("range list is NULL or n < 0"); return SCN_EINVAL; }
-      int64_t prev_end = 0;
+      if (s.n > kMaxRows) { set_error("sampling selects more than 2^31 - 1 rows"); return SCN_EUNSUPPORTED; }
+      // validate every window and bound the total before materialising rows
+      int64_t prev_end = 0, total = 0;
       for (int64_t i = 0; i < s.n; ++i) {
         const int64_t b = s.idx[2 * i], e = s.idx[2 * i + 1];
         if (b < prev_end || e < b || b < 0 || e > n) {
           set_error("ranges must be half-open, ascending, disjoint and within the table");
           return SCN_EINVAL;
         }
+        total += e - b;  // windows are disjoint inside [0, n): no overflow
+        if (total > kMaxRows) { set_error("sampling selects more than 2^31 - 1 rows"); return SCN_EUNSUPPORTED; }
+        prev_end = e;
+      }
+      for (int64_t i = 0; i < s.n; ++i) {
+        const int64_t b = s.idx[2 * i], e = s.idx[2 * i + 1];
         Slice sl;
+        sl.rows.reserve((size_t)(e - b));
         for (int64_t r = b; r < e; ++r) sl.rows.push_back(r);
         out->push_back(std::move(sl));
-        prev_end = e;
       }
       return SCN_OK;
     }
@@ -128,6 +146,20 @@ scn_status resolve_flat(const scn_job* job, Resolved* out) {
   if (out->rows.size() > (size_t)std::numeric_limits<int32_t>::max()) {
     set_error("too many sampled rows");
     return SCN_EUNSUPPORTED;
+  }
+  // every row a call reads (sampled rows, and the successors of the
+  // before-sampling stencil) must be backed by memory
+  const scn_table& t = *job->table;
+  if (t.backed_count > 0) {
+    const int64_t lo = t.backed_first, hi = t.backed_first + t.backed_count;
+    auto backed = [&](int64_t r) { return r >= lo && r < hi; };
+    for (int64_t r : out->rows)
+      if (!backed(r)) { set_error("a sampled row is outside the table's backed rows"); return SCN_EINVAL; }
+    for (const auto& pr : out->pairs)
+      if (!backed(pr.first) || !backed(pr.second)) {
+        set_error("a flow pair reads a row outside the table's backed rows");
+        return SCN_EINVAL;
+      }
   }
   return SCN_OK;
 }

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,9 @@ struct Resolved {
   std::vector<int32_t> pair_slice;                       // slice of each pair
 };
 scn_status resolve_flat(const scn_job* job, Resolved* out);
+
+// Most rows one sampling may select (row positions are int32 on the device).
+constexpr int64_t kMaxRows = std::numeric_limits<int32_t>::max();
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }

@@ -202,3 +202,38 @@ def test_warm_start_params_are_validated():
     # the warm start is a FLOW schedule only
     warm = scn.flow_params(2, 10.0, 5, warm_packet=2, warm_iters=3)
     assert L.scn_workspace_bytes(scn.SCN_OP_SURROGATE, scn._jobs_array([job]), 1, ctypes.byref(warm)) == 0
+
+
+def test_stride_count_does_not_overflow_and_huge_counts_are_refused():
+    t = _cpu_table(2400)
+    big = 2 ** 63 - 1
+    assert scn.count_rows(scn.Job(t, scn.Sampling.stride(big, 1, 2))) == 1
+    assert scn.count_rows(scn.Job(t, scn.Sampling.stride(big - 5, 2399, 2400))) == 1
+    huge = _cpu_table(4)
+    huge.n_frames = 2 ** 40  # validation only: no row is read
+    n = scn.lib().scn_count_rows(ctypes.byref(scn.Job(huge, scn.Sampling.stride(1, 0, 2 ** 40)).cjob))
+    assert n == scn.SCN_EUNSUPPORTED
+    n = scn.lib().scn_count_rows(ctypes.byref(scn.Job(huge, scn.Sampling.range([(0, 2 ** 40)])).cjob))
+    assert n == scn.SCN_EUNSUPPORTED
+
+
+def test_window_views_refuse_rows_outside_the_backed_window():
+    rows = torch.zeros((40, 64 * 48 * 3 // 2), dtype=torch.uint8)
+    t = scn.Table.window(rows, 100, 2400, 64, 48)
+
+    def status(samp):
+        return int(scn.lib().scn_count_rows(ctypes.byref(scn.Job(t, samp).cjob)))
+
+    assert status(scn.Sampling.range([(100, 140)])) == 40
+    assert status(scn.Sampling.gather([100, 139])) == 2
+    assert status(scn.Sampling.stride(3, 100, 140)) == 14
+    assert status(scn.Sampling.gather([99, 120])) == scn.SCN_EINVAL
+    assert status(scn.Sampling.gather([120, 140])) == scn.SCN_EINVAL
+    assert status(scn.Sampling.range([(90, 110)])) == scn.SCN_EINVAL
+    # the before-sampling stencil reads row s + 1: (139, 140) leaves the window
+    assert status(scn.Sampling.range([(100, 140)]).before()) == scn.SCN_EINVAL
+    assert "backed" in scn.lib().scn_last_error().decode()
+    assert status(scn.Sampling.range([(100, 139)]).before()) == 39
+    # the Python wrappers raise before any device work
+    with pytest.raises(scn.ScnError):
+        scn.count_pairs(scn.Job(t, scn.Sampling.gather([10, 120])))
