@@ -201,6 +201,22 @@ scn_status scn_sample_convert(const scn_job* job, int32_t out_w, int32_t out_h, 
 scn_status scn_hist(const scn_job* job, uint32_t* hist, void* ws, size_t ws_bytes,
                     scn_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): scn_hist
+ * without a workspace.  Same kernels and same results as scn_hist; the
+ * sampled-row table that scn_hist stages in `ws` goes to a fixed device array
+ * of SCN_HIST_STATIC_MAX_ROWS int64 entries (512 KiB) that the library holds
+ * on every GPU it runs on until the process ends.  No call allocates or frees
+ * device memory.  Jobs selecting more than SCN_HIST_STATIC_MAX_ROWS rows are
+ * refused with SCN_ENOSPACE.  Every call on one GPU shares that GPU's array
+ * and overwrites the row table of the previous call: calls that overlap on
+ * one GPU (different streams, or different host threads without ordering)
+ * race, so order them on one stream.  Graph capture follows the workspace
+ * rule above, with the array as the workspace.
+ * hist: device, uint32 [M][3][16], overwritten. */
+#define SCN_HIST_STATIC_MAX_ROWS 65536
+scn_status scn_hist_static(const scn_job* job, uint32_t* hist, scn_stream_t stream);
+
 /* Spacing (Sec. 3.2: the inverse of sampling, which aligns a sampled
  * sequence with the dense timeline): the index map of the job's FLOW outputs
  * (its pairs, in order) on the table's n_frames rows, output k placed at the

@@ -62,7 +62,7 @@ class CFlowParams(ctypes.Structure):
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
            "scn_hist_diff", "scn_space_map", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
            "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
-           "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate"]
+           "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate", "scn_hist_static"]
 
 _lib = None
 
@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
     L.scn_sample_convert.restype = ctypes.c_int
     L.scn_hist.argtypes = [P(CJob), vp, vp, ctypes.c_size_t, vp]
     L.scn_hist.restype = ctypes.c_int
+    L.scn_hist_static.argtypes = [P(CJob), vp, vp]
+    L.scn_hist_static.restype = ctypes.c_int
     L.scn_hist_diff.argtypes = [P(CJob), vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_size_t, vp]
     L.scn_hist_diff.restype = ctypes.c_int
     L.scn_space_map.argtypes = [P(CJob), ctypes.c_int32, vp]
@@ -321,6 +323,21 @@ def hist(job: Job, out: Optional[torch.Tensor] = None, stream=None, ws: Optional
     need = workspace_bytes(SCN_OP_HIST, [job])
     w = ws if ws is not None else _ws(dev, need)
     _check(lib().scn_hist(ctypes.byref(job.cjob), out.data_ptr(), w.data_ptr(), w.numel(), _stream(stream)))
+    return out
+
+
+HIST_STATIC_MAX_ROWS = 65536  # SCN_HIST_STATIC_MAX_ROWS
+
+
+def hist_static(job: Job, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """hist() without a workspace: the row table goes to the library's fixed
+    per-GPU array (for callers that cannot allocate; at most
+    HIST_STATIC_MAX_ROWS sampled rows; calls on one GPU must not overlap).
+    The output tensor is the caller's: pass `out` to allocate nothing."""
+    m = count_rows(job)
+    if out is None:
+        out = torch.empty((m, 3, 16), dtype=torch.int32, device=job.table.frames.device)
+    _check(lib().scn_hist_static(ctypes.byref(job.cjob), _ptr(out), _stream(stream)))
     return out
 
 

@@ -92,6 +92,23 @@ def test_hist_validation_before_any_device_work():
     assert L.scn_hist(ctypes.byref(empty.cjob), None, None, 0, None) == scn.SCN_OK
 
 
+def test_hist_static_validation_before_any_device_work():
+    """The allocation-free HIST refuses jobs beyond its fixed row table and
+    bad pointers before it touches a device."""
+    L = scn.lib()
+    big = _cpu_table(scn.HIST_STATIC_MAX_ROWS + 2, 2, 2)
+    out = torch.zeros(48, dtype=torch.int32)
+    over = scn.Job(big, scn.Sampling.stride(1, 0, scn.HIST_STATIC_MAX_ROWS + 1))
+    assert L.scn_hist_static(ctypes.byref(over.cjob), out.data_ptr(), None) == scn.SCN_ENOSPACE
+    assert "65536" in L.scn_last_error().decode()
+    job = scn.Job(_cpu_table(8), scn.Sampling.stride(1, 0, 8))
+    assert L.scn_hist_static(ctypes.byref(job.cjob), None, None) == scn.SCN_EINVAL
+    empty = scn.Job(_cpu_table(8), scn.Sampling.gather([]))
+    assert L.scn_hist_static(ctypes.byref(empty.cjob), None, None) == scn.SCN_OK
+    bad = scn.Job(_cpu_table(8), scn.Sampling.gather([3, 3]))
+    assert L.scn_hist_static(ctypes.byref(bad.cjob), out.data_ptr(), None) == scn.SCN_EINVAL
+
+
 def test_hist_diff_validation_before_any_device_work():
     t = _cpu_table(20)
     job = scn.Job(t, scn.Sampling.range([(0, 3), (5, 8)]))  # 6 rows, 4 pairs (none across windows)
