@@ -33,3 +33,23 @@ def c1_frames(n=16, noise=2.0, w=320, h=240, seed=1):
 
 def frame_np(tab: torch.Tensor, row: int, width: int, height: int, pitch: int) -> np.ndarray:
     return tab[row].cpu().numpy().reshape(height * 3 // 2, pitch)
+
+
+def _oracle_flow_job(args):
+    from oracle import hs as OH
+    y1, y2, levels, alpha, iters = args
+    u, v = OH.hs_flow(y1, y2, levels=levels, alpha=alpha, iters=iters)
+    return np.stack([u, v])
+
+
+def oracle_flows(luma_pairs, levels, alpha=10.0, iters=50):
+    """FP64 oracle flow of each (Y1, Y2) luma pair, one pair per process
+    (spawned interpreters that never touch the GPU)."""
+    import multiprocessing as mp
+    import os
+    jobs = [(a, b, levels, alpha, iters) for a, b in luma_pairs]
+    if len(jobs) <= 1:
+        return [_oracle_flow_job(j) for j in jobs]
+    n = max(1, min(len(jobs), len(os.sched_getaffinity(0)), 16))
+    with mp.get_context("spawn").Pool(n) as pool:
+        return pool.map(_oracle_flow_job, jobs, chunksize=1)

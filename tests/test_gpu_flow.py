@@ -9,7 +9,7 @@ import synth
 from oracle import hs as OH
 from oracle import sampling as OS
 from oracle import warm as OW
-from tests.helpers import c1_frames, frame_np, need_gpu, table_from_frames
+from tests.helpers import c1_frames, frame_np, need_gpu, oracle_flows, table_from_frames
 
 pytestmark = pytest.mark.gpu
 
@@ -201,23 +201,30 @@ def test_unsampled_rows_are_never_read():
 
 
 def test_flow_c2_1080p_sampled_pairs():
-    """1080p layered-affine stream, STRIDE-24: three of the 99 pairs against the oracle."""
+    """The benchmark's 1080p call: the layered-affine stream sampled STRIDE-24
+    (99 pairs) and by the seeded 1% GATHER (23 pairs), both jobs in one call
+    as the benchmark times them; three STRIDE pairs and two GATHER pairs
+    against the oracle."""
     need_gpu()
     W, H, N = 1920, 1080, 2400
     scene = synth.layered_scene(2, W, H)
     rows = OS.rows("stride", N, start=0, step=24, stop=N)
+    grows = synth.gather_list(2, N, 0.01)
     fb = W * H * 3 // 2
     tab = torch.full((N, fb), 0xFF, dtype=torch.uint8, device="cuda")
-    for r in rows:
+    for r in sorted(set(rows) | set(grows)):
         tab[r] = scene.nv12(r, device="cuda").reshape(-1)
-    job = scn.Job(scn.Table.from_tensor(tab, W, H), scn.Sampling.stride(24, 0, N))
-    (f,) = scn.flow([job], scn.flow_params(levels=4))
-    assert f.shape == (99, 2, H, W)
+    t = scn.Table.from_tensor(tab, W, H)
+    js, jg = scn.Job(t, scn.Sampling.stride(24, 0, N)), scn.Job(t, scn.Sampling.gather(grows))
+    fs, fg = scn.flow([js, jg], scn.flow_params(levels=4))
+    assert fs.shape == (99, 2, H, W) and fg.shape == (23, 2, H, W)
     prs = OS.pairs("stride", N, start=0, step=24, stop=N)
-    for k in [0, 50, 98]:
-        exp = _oracle_pairs(tab, [prs[k]], W, H, W, 4)[0]
-        d = _maxdiff(f[k].cpu().numpy(), exp)
-        print("C2 pair %d max |d| = %.3g" % (k, d))
+    pgs = OS.pairs("gather", N, idx=grows)
+    cases = [("stride", k, fs, prs[k]) for k in (0, 50, 98)] + [("gather", k, fg, pgs[k]) for k in (0, 22)]
+    exp = oracle_flows([(frame_np(tab, a, W, H, W)[:H], frame_np(tab, b, W, H, W)[:H]) for *_, (a, b) in cases], 4)
+    for (kind, k, f, pr), e in zip(cases, exp):
+        d = _maxdiff(f[k].cpu().numpy(), e)
+        print("C2 %s pair %d %s max |d| = %.3g" % (kind, k, pr, d))
         assert d <= TOL
 
 

@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 
 # one BF16 ulp is 2^-8 relative; sums of many rounded terms stay near it
 REL_FWD = 2e-3
-REL_GRAD = 1e-2
+# dX and dW: per-tensor relative L2 within about one BF16 ulp (2^-7 ~ 8e-3):
+# gradients are rounded to BF16 between layers, the oracle keeps them in FP64
+REL_GRAD = 8e-3
 
 
 def _rel_l2(a, b):
@@ -121,32 +123,44 @@ def test_forward_persistent_rounds_are_batch_invariant():
     assert r <= REL_FWD
 
 
-def test_gradient_parity():
-    need_gpu()
-    W, H = 64, 48
-    tab, job = _pairs_table(W, H, 3, 12)
+def _grad_parity(W, H, n_pairs, seed):
+    tab, job = _pairs_table(W, H, n_pairs + 1, seed)
     master, p64 = _master(_params(2))
     net = scn.net_pack(master)
     g = torch.Generator().manual_seed(5)
-    target = torch.randn((2, 2, H, W), generator=g, dtype=torch.float32) * 2.0
+    target = torch.randn((n_pairs, 2, H, W), generator=g, dtype=torch.float32) * 2.0
     grads, loss = scn.surrogate_grads([job], net, [target.cuda()])
     grads = grads.cpu().numpy().astype(np.float64)
     tot_loss = 0.0
     tot = None
-    for k in range(2):
+    for k in range(n_pairs):
         y1 = frame_np(tab, k, W, H, W)[:H]
         y2 = frame_np(tab, k + 1, W, H, W)[:H]
         l, gr = S.train_step_grads(p64, y1, y2, target[k].numpy().astype(np.float64))
-        tot_loss += l / 2
-        gv = _flat(gr) / 2
+        tot_loss += l / n_pairs
+        gv = _flat(gr) / n_pairs
         tot = gv if tot is None else tot + gv
     assert abs(float(loss.item()) - tot_loss) <= 1e-3 * abs(tot_loss)
     gp = _unflat(grads)
     ge = _unflat(tot)
     for name in ge:
         r = _rel_l2(gp[name], ge[name])
-        print("%s grad rel L2 %.2e" % (name, r))
+        print("%dx%d x%d %s grad rel L2 %.2e" % (W, H, n_pairs, name, r))
         assert r <= REL_GRAD, name
+
+
+def test_gradient_parity():
+    need_gpu()
+    _grad_parity(64, 48, 2, 12)
+
+
+def test_gradient_parity_multi_chunk():
+    """2 pairs of 520 x 392: every layer's weight gradient spans several
+    2048-pixel partial-sum chunks, the last one ragged (conv3: 2 x 65 x 49 =
+    6,370 output pixels, conv1: 2 x 260 x 196 = 101,920), so the chunked
+    partials and their fixed-order reduction are compared with the oracle."""
+    need_gpu()
+    _grad_parity(520, 392, 2, 16)
 
 
 def test_adam_step_parity():
@@ -317,3 +331,104 @@ def test_trained_network_gain():
     e_gated = epe(gated, plain_b)
     print("1080p held-out: gated mean EPE %.3f (fallback %d/%d)" % (e_gated, int(fb.sum()), n - 1))
     assert e_gated <= 0.5
+
+
+def _trained():
+    import os
+    from paper_1805_07339_amd import train as T
+    if not os.path.exists(T.DEFAULT_WEIGHTS):
+        pytest.skip("no trained checkpoint")
+    master, meta = T.load(T.DEFAULT_WEIGHTS, "cuda")
+    return master, _unflat(master.cpu().numpy().astype(np.float64)), meta
+
+
+def _c2_table(W=1920, H=1080, N=2400):
+    from oracle import sampling as OS
+    scene = synth.layered_scene(2, W, H)
+    rows = OS.rows("stride", N, start=0, step=24, stop=N)
+    grows = synth.gather_list(2, N, 0.01)
+    tab = torch.full((N, W * H * 3 // 2), 0xFF, dtype=torch.uint8, device="cuda")
+    for r in sorted(set(rows) | set(grows)):
+        tab[r] = scene.nv12(r, device="cuda").reshape(-1)
+    t = scn.Table.from_tensor(tab, W, H)
+    return tab, [scn.Job(t, scn.Sampling.stride(24, 0, N)), scn.Job(t, scn.Sampling.gather(grows))]
+
+
+# Per-pixel bound of the 1080p forward in BF16 ulps of the pair's flow scale:
+# |d| <= FWD_PIX_ULPS * 2^-8 * max |flow| on every pixel.  The two sides share
+# every BF16 rounding point, but FP32 and FP64 sums land on different sides of
+# a rounding boundary now and then, and each such flip moves a neighbourhood
+# of later activations by about one ulp; measured up to 0.36 ulps on the two
+# pairs below.
+FWD_PIX_ULPS = 1
+
+
+def test_forward_1080p_trained_weights():
+    """The benchmark's network input (960 x 540 half-resolution pairs of the
+    1080p stream) through the packaged trained weights: relative L2 and a
+    per-pixel bound against the oracle's forward, on one STRIDE-24 and one
+    GATHER pair."""
+    need_gpu()
+    from oracle import sampling as OS
+    master, p64, _ = _trained()
+    net = scn.net_pack(master)
+    tab, jobs = _c2_table()
+    flows = scn.surrogate_infer(jobs, net)
+    W, H = 1920, 1080
+    prs = [OS.pairs("stride", 2400, start=0, step=24, stop=2400)[40],
+           OS.pairs("gather", 2400, idx=synth.gather_list(2, 2400, 0.01))[11]]
+    for (a, b), f in zip(prs, (flows[0][40], flows[1][11])):
+        half, _ = S.forward(p64, S.net_input(frame_np(tab, a, W, H, W)[:H], frame_np(tab, b, W, H, W)[:H]))
+        exp = S.flow_full(half)
+        got = f.cpu().numpy().astype(np.float64)
+        r = _rel_l2(got, exp)
+        scale = float(np.abs(exp).max())
+        ulps = float(np.abs(got - exp).max()) / (2.0 ** -8 * scale)
+        print("1080p pair %s: forward rel L2 %.2e, max |d| %.3g px = %.2f BF16 ulps of max |flow| %.3g"
+              % ((a, b), r, float(np.abs(got - exp).max()), ulps, scale))
+        assert r <= REL_FWD
+        assert ulps <= FWD_PIX_ULPS
+
+
+def test_gated_fallback_1080p_benchmark_call():
+    """The benchmark's gated call (122 pairs of 1080p, trained weights) with
+    tau set between the pairs' residuals, so that about a fifth of the pairs
+    fall back: routing follows r > tau exactly, fallen-back pairs equal the
+    plain solver's flow of the same call bit for bit (one of them is also
+    checked against the oracle), kept pairs equal the network's flow bit for
+    bit."""
+    need_gpu()
+    from oracle import sampling as OS
+    from tests.helpers import oracle_flows
+    master, _, _ = _trained()
+    net = scn.net_pack(master)
+    tab, jobs = _c2_table()
+    prm = scn.flow_params(levels=4)
+    plain = scn.flow(jobs, prm)
+    net_only = scn.surrogate_infer(jobs, net)
+    _, _, res = scn.flow_surrogate(jobs, net, float("inf"), prm)
+    r = torch.cat(res).cpu().numpy()
+    tau = float(np.quantile(r, 0.8))
+    mix, fb, res2 = scn.flow_surrogate(jobs, net, tau, prm)
+    fbv = torch.cat(fb).cpu().numpy()
+    assert np.array_equal(torch.cat(res2).cpu().numpy(), r)
+    assert fbv.tolist() == [int(x > tau) for x in r]
+    n_fb = int(fbv.sum())
+    print("tau %.4f: %d of %d pairs fall back" % (tau, n_fb, len(r)))
+    assert 10 <= n_fb <= 40
+    first_fb = None
+    for j in range(2):
+        f = fb[j].cpu().numpy()
+        for k in range(len(f)):
+            ref = plain[j][k] if f[k] else net_only[j][k]
+            assert torch.equal(mix[j][k], ref), (j, k)
+            if f[k] and first_fb is None:
+                first_fb = (j, k)
+    j, k = first_fb
+    pr = (OS.pairs("stride", 2400, start=0, step=24, stop=2400) if j == 0 else
+          OS.pairs("gather", 2400, idx=synth.gather_list(2, 2400, 0.01)))[k]
+    (e,) = oracle_flows([(frame_np(tab, pr[0], 1920, 1080, 1920)[:1080],
+                          frame_np(tab, pr[1], 1920, 1080, 1920)[:1080])], 4)
+    d = float(np.abs(mix[j][k].cpu().numpy().astype(np.float64) - e).max())
+    print("fallen-back pair %s vs oracle: max |d| %.3g px" % (pr, d))
+    assert d <= 1e-3
