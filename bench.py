@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 W, H, N_ROWS = 1920, 1080, 2400
 LEVELS, ALPHA, ITERS = 4, 10.0, 50
+FB_ITERS = 3  # Farnebäck displacement iterations per level
 HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -158,6 +159,57 @@ def extra_legs(scn, torch, dev, tab, table, scene, stride_rows, prm, stream):
             "warm_ms_per_call": seq_ms["warm"], "speedup": seq_ms["cold"] / seq_ms["warm"],
             "mean_epe_vs_cold_px": warm_epe, "note": "128 consecutive 1080p pairs of the stream; flow only"}
     return before, warm
+
+
+def farneback_leg(scn, torch, dev, jobs, hists, ws_hist, stream, m_total, p_total, steps, warmup):
+    """The same step with the Farnebäck solver (polynomial expansion, the
+    paper's FLOW kernel) in place of Horn-Schunck: HIST on the 124 frames and
+    Farnebäck flow (4 levels, 3 iterations, 5 x 5 expansion with sigma 1.1,
+    15 x 15 box, lambda 1e-3) on the 122 pairs.  Roofline of the displacement
+    kernel: per pixel and iteration it reads both frames' expansion planes
+    (2 x 20 B) and the prior flow (8 B) and writes the new flow (8 B)."""
+    from oracle.hs import level_sizes
+    prm = scn.farneback_params(LEVELS, FB_ITERS)
+    flows = [torch.empty((scn.count_pairs(j), 2, H, W), dtype=torch.float32, device=dev) for j in jobs]
+    ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, jobs, prm), dtype=torch.uint8, device=dev)
+
+    def step():
+        for j, h, w in zip(jobs, hists, ws_hist):
+            scn.hist(j, out=h, stream=stream, ws=w)
+        scn.flow(jobs, prm, outs=flows, stream=stream, ws=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    scn.timing_enable(True, 1 << 16)
+    scn.timing_reset()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    kern = {k: scn.timing_read(k) for k in ["hist16", "pyr_down", "fb_poly", "fb_disp"]}
+    scn.timing_enable(False)
+    px_levels = sum(w * h for w, h in level_sizes(W, H, LEVELS))
+    disp_bytes = 56.0 * px_levels * FB_ITERS * p_total * steps
+    disp_ms, disp_n = kern["fb_disp"]
+    # every sampled frame is expanded once per level (its <= 2 pairs share it)
+    poly_bytes = (21.0 * W * H + 24.0 * (px_levels - W * H)) * m_total * steps
+    poly_ms, poly_n = kern["fb_poly"]
+    del flows, ws
+    return {"value": m_total * steps / dt, "unit": "frames/s", "ms_per_step": dt / steps * 1e3,
+            "params": {"levels": LEVELS, "iters": FB_ITERS, "poly_n": 2, "sigma": 1.1, "win": 7, "lambda": 1e-3},
+            "ms_per_step_by_kernel": {k: v[0] / steps for k, v in kern.items()},
+            "fb_disp": {"bound": "hbm", "algorithmic_bytes_per_px_iter": 56, "achieved_GBps":
+                        disp_bytes / (disp_ms * 1e-3) / 1e9, "frac": disp_bytes / (disp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "launches": disp_n, "avg_launch_ms": disp_ms / max(disp_n, 1)},
+            "fb_poly": {"bound": "hbm", "algorithmic_bytes_per_px": "1 (level 0, u8) or 4 in + 20 out",
+                        "achieved_GBps": poly_bytes / (poly_ms * 1e-3) / 1e9,
+                        "frac": poly_bytes / (poly_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "launches": poly_n},
+            "note": "HIST + Farnebäck flow over the same 124 frames / 122 pairs as the headline step"}
 
 
 def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_total, args):
@@ -638,6 +690,7 @@ def main():
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--tau", type=float, default=None, help="gate threshold (default: the calibrated one)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-farneback", action="store_true", help="skip the Farnebäck leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the stencil-before-sampling and warm-start legs (profiled runs: their Jacobi "
                          "launches would follow the timed step's)")
@@ -768,6 +821,9 @@ def main():
     if not args.no_extras:
         before_leg, warm_leg = extra_legs(scn, torch, dev, tab, table, scene, stride_rows, prm, stream)
 
+    farneback = (None if args.no_farneback else
+                 farneback_leg(scn, torch, dev, jobs, hists, ws_hist, stream, m_total, p_total, args.steps,
+                               args.warmup))
     surrogate = (None if args.no_surrogate else
                  surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
     if args.calib_copy:
@@ -822,6 +878,7 @@ def main():
                           "avg_launch_ms": conv_ms / max(conv_n, 1), "frames_per_launch": 400,
                           "counter_GBps": (ctr_kv["convert_bytes_per_launch"] / (conv_ms / max(conv_n, 1) * 1e-3) / 1e9
                                            if "convert_bytes_per_launch" in ctr_kv else None)},
+        "farneback": farneback,
         "surrogate": surrogate,
         "surrogate_over_plain_frames_per_s": (surrogate["value"] / (m_total * args.steps / dt)
                                               if surrogate and "value" in surrogate else None),

@@ -147,7 +147,27 @@ typedef struct {
  * at full resolution only, starting from its predecessor's flow (I2 warped
  * by it, the constraint linearised about it), with `warm_iters` >= 0 Jacobi
  * iterations.  Results depend on G, not on batching or chunking.  0 or 1:
- * every pair cold (warm_iters ignored). */
+ * every pair cold (warm_iters ignored).
+ *
+ * `solver` selects the method: SCN_SOLVER_HS (0, a zero-initialised field)
+ * is the Horn-Schunck solver above.  SCN_SOLVER_FARNEBACK (1) is Farnebäck's
+ * two-frame motion estimation by polynomial expansion (Farnebäck, SCIA 2003),
+ * the FLOW kernel of the paper's microbenchmark (Sec. 5.1.2), on the same
+ * pyramid and coarse-to-fine scheme: at every level each frame's
+ * neighbourhoods are fitted by a quadratic t'A t + b't + c (weighted least
+ * squares over the clamped (2 fb_poly_n + 1)^2 window, Gaussian applicability
+ * with standard deviation fb_sigma); then `iters` times per level, from the
+ * prior displacement d (the coarser level's result x 2 at the first
+ * iteration, zero at the coarsest level), frame 2's coefficients are sampled
+ * bilinearly at x + d, A = (A1 + A2(x + d)) / 2 and
+ * db = -(b2(x + d) - b1) / 2 + A d, and the new displacement solves
+ * (mean(A'A) + fb_lambda I) d = mean(A'db), the means taken over the clamped
+ * (2 fb_win + 1)^2 box around each pixel.  alpha, sweeps_per_pass and
+ * tile_variant are ignored; warm_packet must be 0 or 1.  Supported:
+ * fb_poly_n = 2, fb_sigma in [0.5, 8], fb_win in [0, 8], fb_lambda in
+ * (0, 1e6]; other values are SCN_EUNSUPPORTED (fb_poly_n) or SCN_EINVAL.
+ * FP32 throughout; results do not depend on batching or chunking. */
+enum { SCN_SOLVER_HS = 0, SCN_SOLVER_FARNEBACK = 1 };
 typedef struct {
   int32_t levels;
   float alpha;
@@ -156,6 +176,11 @@ typedef struct {
   int32_t tile_variant;
   int32_t warm_packet;
   int32_t warm_iters;
+  int32_t solver;
+  int32_t fb_poly_n;
+  float fb_sigma;
+  int32_t fb_win;
+  float fb_lambda;
 } scn_flow_params;
 
 enum { SCN_RGB24 = 0, SCN_GRAY8 = 1 };
@@ -243,8 +268,8 @@ scn_status scn_space_map(const scn_job* job, int32_t mode, int64_t* map);
 scn_status scn_hist_diff(const scn_job* job, const uint32_t* hist, uint32_t threshold, uint32_t* diff,
                          uint8_t* cut, void* ws, size_t ws_bytes, scn_stream_t stream);
 
-/* FLOW (Sec. 3.2 stencil S[0,1], Sec. 5.1.2): dense pyramidal Horn-Schunck
- * optical flow, FP32, over the pairs of every job (consecutive sampled rows
+/* FLOW (Sec. 3.2 stencil S[0,1], Sec. 5.1.2): dense pyramidal optical flow
+ * (Horn-Schunck, or Farnebäck with p->solver), FP32, over the pairs of every job (consecutive sampled rows
  * of each slice, or original neighbours (s, s+1) of each sampled row s with
  * SCN_STENCIL_BEFORE).  Jobs may differ in resolution; all of their pairs
  * are computed by one batch of launches.  Each frame's pyramid is built
@@ -299,7 +324,8 @@ scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* 
 /* FLOW with the surrogate and a residual gate: per pair the network's flow w
  * is kept if r = mean over pixels of |Y2(x + w) - Y1(x)| (luma, clamped
  * bilinear warp) is <= gate_tau, else the pair is recomputed by scn_flow's
- * plain Horn-Schunck solver with fallback_p.  The decision is taken on the
+ * plain Horn-Schunck solver with fallback_p (fallback_p->solver must be
+ * SCN_SOLVER_HS, else SCN_EUNSUPPORTED).  The decision is taken on the
  * device (no host synchronisation).  flow[j]: device [P_j][2][H][W];
  * fell_back[j] (device, uint8 [P_j], may be NULL) receives 1 for recomputed
  * pairs; residual[j] (device, float [P_j], may be NULL) receives r. */
@@ -313,7 +339,8 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
  * launches until the next scn_timing_reset).  scn_timing_read synchronises
  * those events and returns the summed duration and launch count of one
  * kernel class ("hist16", "nv12_rgb24", "nv12_resize", "luma_copy",
- * "pyr_down", "hs_setup", "hs_jacobi", "conv_fwd", "conv_dx",
+ * "pyr_down", "hs_setup", "hs_jacobi", "fb_poly", "fb_disp",
+ * "conv_fwd", "conv_dx",
  * "conv_dw", "flow_up", "gate"), or of a finer class ("hs_jacobi_l0" ..
  * "hs_jacobi_l6" per pyramid level, "conv_fwd1" .. "conv_fwd6" per layer);
  * nested classes time the same launches.  It returns SCN_ENOSPACE if

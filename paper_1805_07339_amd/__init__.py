@@ -55,7 +55,8 @@ class CJob(ctypes.Structure):
 class CFlowParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("alpha", ctypes.c_float), ("iters", ctypes.c_int32),
                 ("sweeps_per_pass", ctypes.c_int32), ("tile_variant", ctypes.c_int32), ("warm_packet", ctypes.c_int32),
-                ("warm_iters", ctypes.c_int32)]
+                ("warm_iters", ctypes.c_int32), ("solver", ctypes.c_int32), ("fb_poly_n", ctypes.c_int32),
+                ("fb_sigma", ctypes.c_float), ("fb_win", ctypes.c_int32), ("fb_lambda", ctypes.c_float)]
 
 
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
@@ -249,12 +250,25 @@ def _jobs_array(jobs: Sequence[Job]):
     return arr
 
 
+SCN_SOLVER_HS, SCN_SOLVER_FARNEBACK = 0, 1
+
+
 def flow_params(levels: int = 4, alpha: float = 10.0, iters: int = 50, sweeps_per_pass: int = 0,
                 tile_variant: int = 0, warm_packet: int = 0, warm_iters: int = 0) -> CFlowParams:
     """Horn-Schunck parameters; warm_packet >= 2 turns on the temporal warm
     start (packets of that many pairs, later pairs solved at full resolution
     from their predecessor's flow with warm_iters iterations)."""
-    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_variant, warm_packet, warm_iters)
+    return CFlowParams(levels, alpha, iters, sweeps_per_pass, tile_variant, warm_packet, warm_iters,
+                       SCN_SOLVER_HS, 0, 0.0, 0, 0.0)
+
+
+def farneback_params(levels: int = 4, iters: int = 3, poly_n: int = 2, sigma: float = 1.1, win: int = 7,
+                     lam: float = 1e-3) -> CFlowParams:
+    """Farnebäck parameters for scn.flow: `iters` displacement estimates per
+    level, (2 poly_n + 1)^2 expansion window with Gaussian applicability of
+    standard deviation `sigma`, (2 win + 1)^2 averaging box, regulariser
+    `lam`."""
+    return CFlowParams(levels, 0.0, iters, 0, 0, 0, 0, SCN_SOLVER_FARNEBACK, poly_n, sigma, win, lam)
 
 
 def count_rows(job: Job) -> int:
@@ -395,7 +409,8 @@ def sample_convert(job: Job, out_w: Optional[int] = None, out_h: Optional[int] =
 
 def flow(jobs: Sequence[Job], params: Optional[CFlowParams] = None, outs: Optional[List[torch.Tensor]] = None,
          stream=None, ws: Optional[torch.Tensor] = None, ws_bytes: Optional[int] = None) -> List[torch.Tensor]:
-    """Pyramidal Horn-Schunck flow for every job -> list of float32 [P_j, 2, H_j, W_j]."""
+    """Pyramidal Horn-Schunck (or, with farneback_params, Farnebäck) flow for
+    every job -> list of float32 [P_j, 2, H_j, W_j]."""
     params = flow_params() if params is None else params
     if outs is None:
         outs = []

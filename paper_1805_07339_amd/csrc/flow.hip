@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -1000,6 +1001,130 @@ JacobiChoice default_choice(const LevelGeom& g, int32_t iters) {
 
 #include "tune.inc"
 
+namespace {
+#include "farneback.inc"
+}  // namespace
+
+// Levels 1..L-1 of every frame slot of a chunk.
+scn_status launch_pyramids(const ChunkPtrs& c, const FlowGroup& grp, const FlowChunk& ch, int32_t L, hipStream_t s) {
+  for (int32_t l = 1; l < L; ++l) {
+    const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
+    const int32_t tiles_x = (dg.w + kPyrTW - 1) / kPyrTW, tiles_y = (dg.h + kPyrTH - 1) / kPyrTH;
+    const int64_t tpf = (int64_t)tiles_x * tiles_y;
+    const int64_t grid = tpf * ch.n_frames;
+    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    KernelTimer timer("pyr_down", s);
+    if (l == 1)
+      hipLaunchKernelGGL(k_pyr_down<true>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
+    else
+      hipLaunchKernelGGL(k_pyr_down<false>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
+    SCN_LAUNCHED("pyramid launch");
+  }
+  return SCN_OK;
+}
+
+// Expansion constants for the Gaussian applicability of standard deviation
+// sigma over the 5 x 5 window (double precision, rounded once to float).
+FbConst fb_constants(float sigma) {
+  double gg[3];
+  for (int t = 0; t < 3; ++t) gg[t] = std::exp(-(double)(t * t) / (2.0 * (double)sigma * sigma));
+  // 1-D sums of g(t) t^k over t = -2..2
+  const double S0 = gg[0] + 2 * gg[1] + 2 * gg[2], S2 = 2 * gg[1] + 8 * gg[2], S4 = 2 * gg[1] + 32 * gg[2];
+  // 2-D sums of a(t) = g(tx) g(ty) times the basis products
+  const double s0 = S0 * S0, s2 = S2 * S0, s4 = S4 * S0, s22 = S2 * S2;
+  // inverse of the coupled block over the basis (1, tx^2, ty^2)
+  const double M[3][3] = {{s0, s2, s2}, {s2, s4, s22}, {s2, s22, s4}};
+  const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                     M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                     M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  auto inv = [&](int r, int col) {  // (adj M)[r][col] / det = cofactor(col, r) / det
+    const int r0 = (col + 1) % 3, r1 = (col + 2) % 3, c0 = (r + 1) % 3, c1 = (r + 2) % 3;
+    return (M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0]) / det;
+  };
+  FbConst k;
+  k.g0 = (float)gg[0];
+  k.g1 = (float)gg[1];
+  k.g2 = (float)gg[2];
+  k.inv_s2 = (float)(1.0 / s2);
+  k.half_inv_s22 = (float)(0.5 / s22);
+  k.i10 = (float)inv(1, 0);
+  k.i11 = (float)inv(1, 1);
+  k.i12 = (float)inv(1, 2);
+  k.i20 = (float)inv(2, 0);
+  k.i21 = (float)inv(2, 1);
+  k.i22 = (float)inv(2, 2);
+  return k;
+}
+
+// Farneback flow of one chunk: pyramids, then per level (coarse to fine) the
+// expansion of every frame slot and `iters` displacement passes over every
+// pair, the first from the coarser level's flow.
+scn_status run_fb_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowChunk& ch,
+                        const scn_flow_params& prm, void* ws, hipStream_t s) {
+  uint8_t* base = (uint8_t*)ws;
+  const int32_t L = plan.levels;
+  scn_status st;
+  ChunkPtrs c;
+  c.frames = (const FrameDesc*)(base + ch.frames_off);
+  c.pairs = (const PairDesc*)(base + ch.pairs_off);
+  c.pyr = (float*)(base + plan.scratch_off);
+  c.pyr_floats = (int64_t)grp.pyr_floats;
+  c.scratch = (float*)(base + plan.scratch_off + chunk_pyr_bytes(grp, ch));
+  c.pair_floats = (int64_t)grp.pair_floats;
+  c.n_pairs = ch.n_pairs;
+  c.n_frames = ch.n_frames;
+  c.active = nullptr;
+  c.factive = nullptr;
+  c.act_list = nullptr;
+  c.act_count = nullptr;
+  if (prm.iters == 0) {  // zero prior at every level: the flow is zero
+    const int64_t per = 2 * (int64_t)grp.w * grp.h, blocks = (per * ch.n_pairs + 255) / 256;
+    if (blocks > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    KernelTimer timer("fb_disp", s);
+    hipLaunchKernelGGL(k_fb_zero, dim3((unsigned)blocks), dim3(256), 0, s, c, per);
+    SCN_LAUNCHED("zero flow launch");
+    return SCN_OK;
+  }
+  if ((st = launch_pyramids(c, grp, ch, L, s)) != SCN_OK) return st;
+  const FbConst k = fb_constants(prm.fb_sigma);
+  const int32_t m = prm.fb_win;
+  const FbDisp dp{m, (float)(1.0 / ((2.0 * m + 1) * (2.0 * m + 1))), prm.fb_lambda, (int64_t)grp.exp_off};
+  int32_t result = -1;  // buffer code holding the coarser level's flow
+  for (int32_t l = L - 1; l >= 0; --l) {
+    const LevelGeom g = level_geom(grp, l);
+    {
+      const int32_t tiles_x = (g.w + kFpTW - 1) / kFpTW, tiles_y = (g.h + kFpTH - 1) / kFpTH;
+      const int64_t tpf = (int64_t)tiles_x * tiles_y, grid = tpf * ch.n_frames;
+      if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+      KernelTimer timer("fb_poly", s);
+      if (l == 0)
+        hipLaunchKernelGGL(k_fb_poly<true>, dim3((unsigned)grid), dim3(256), 0, s, c, g, k, dp.exp_off, tiles_x,
+                           (int32_t)tpf);
+      else
+        hipLaunchKernelGGL(k_fb_poly<false>, dim3((unsigned)grid), dim3(256), 0, s, c, g, k, dp.exp_off, tiles_x,
+                           (int32_t)tpf);
+      SCN_LAUNCHED("expansion launch");
+    }
+    const int32_t tiles_x = (g.w + kFdTW - 1) / kFdTW, tiles_y = (g.h + kFdTH - 1) / kFdTH;
+    const int64_t tpp = (int64_t)tiles_x * tiles_y, grid = tpp * ch.n_pairs;
+    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
+    int32_t cur = result;
+    for (int32_t it = 0; it < prm.iters; ++it) {
+      const int32_t mode = it > 0 ? 2 : (result < 0 ? 0 : 1);
+      const int32_t dst = (l == 0 && it == prm.iters - 1) ? 2 : (cur < 0 ? 0 : 1 - cur);
+      KernelTimer timer("fb_disp", s);
+      const dim3 gd((unsigned)grid), bd(256);
+      if (mode == 0) hipLaunchKernelGGL(k_fb_disp<0>, gd, bd, 0, s, c, g, dp, 0, dst, tiles_x, (int32_t)tpp);
+      else if (mode == 1) hipLaunchKernelGGL(k_fb_disp<1>, gd, bd, 0, s, c, g, dp, cur, dst, tiles_x, (int32_t)tpp);
+      else hipLaunchKernelGGL(k_fb_disp<2>, gd, bd, 0, s, c, g, dp, cur, dst, tiles_x, (int32_t)tpp);
+      SCN_LAUNCHED("displacement launch");
+      cur = dst;
+    }
+    result = cur;
+  }
+  return SCN_OK;
+}
+
 // Flow of one chunk of pairs (pyramids, then coarse-to-fine warp, coef and
 // Jacobi).  `active` / `factive` (device, per pair / per frame slot) restrict
 // the work to a subset of the chunk's pairs (NULL: all).
@@ -1028,19 +1153,7 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
   c.act_count = act_count;
   // pyramids of every frame slot of the chunk (a warm solve reads level 0
   // straight from the table)
-  for (int32_t l = 1; l < (warm ? 1 : L); ++l) {
-    const LevelGeom sg = level_geom(grp, l - 1), dg = level_geom(grp, l);
-    const int32_t tiles_x = (dg.w + kPyrTW - 1) / kPyrTW, tiles_y = (dg.h + kPyrTH - 1) / kPyrTH;
-    const int64_t tpf = (int64_t)tiles_x * tiles_y;
-    const int64_t grid = tpf * ch.n_frames;
-    if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
-    KernelTimer timer("pyr_down", s);
-    if (l == 1)
-      hipLaunchKernelGGL(k_pyr_down<true>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
-    else
-      hipLaunchKernelGGL(k_pyr_down<false>, dim3((unsigned)grid), dim3(256), 0, s, c, sg, dg, tiles_x, (int32_t)tpf);
-    SCN_LAUNCHED("pyramid launch");
-  }
+  if ((st = launch_pyramids(c, grp, ch, warm ? 1 : L, s)) != SCN_OK) return st;
   int32_t result = -1;  // buffer code holding the coarser level's flow
   for (int32_t l = warm ? 0 : L - 1; l >= 0; --l) {
     const LevelGeom g = level_geom(grp, l);
@@ -1102,6 +1215,10 @@ scn_status run_flow(const FlowPlan& plan, const scn_flow_params& prm, void* ws, 
   uint8_t* base = (uint8_t*)ws;
   for (const FlowGroup& grp : plan.groups)
     for (const FlowChunk& ch : grp.chunks) {
+      if (plan.solver == SCN_SOLVER_FARNEBACK) {
+        if ((st = run_fb_chunk(plan, grp, ch, prm, ws, s)) != SCN_OK) return st;
+        continue;
+      }
       if (!warm) {
         if ((st = run_flow_chunk(plan, grp, ch, prm, ws, nullptr, nullptr, nullptr, nullptr, s, false)) != SCN_OK)
           return st;

@@ -43,6 +43,9 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
   scn_status st = check_flow_params(p, nullptr);
   if (st != SCN_OK) return st;
   plan->levels = p->levels;
+  plan->solver = p->solver;
+  const bool fb = p->solver == SCN_SOLVER_FARNEBACK;
+  if (fb && extra) { set_error("the surrogate's fallback runs the Horn-Schunck solver only"); return SCN_EUNSUPPORTED; }
   const bool warm = p->warm_packet >= 2;
   if (warm && extra) { set_error("the warm start applies to scn_flow only"); return SCN_EINVAL; }
   if (warm) extra = warm_extra;
@@ -74,8 +77,10 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
         g.lvl_off[l] = off;
         off += (size_t)g.dims[l].w * g.dims[l].h;
       }
-      g.pyr_floats = off;
-      g.pair_floats = (size_t)kPairPlanes * t.width * t.height;
+      const size_t n0 = (size_t)t.width * t.height;
+      g.exp_off = off;
+      g.pyr_floats = off + (fb ? (size_t)kFbExpPlanes * n0 : 0);
+      g.pair_floats = (size_t)(fb ? kFbPairPlanes : kPairPlanes) * n0;
       g.extra_pair_bytes = extra ? extra(t.width, t.height) : 0;
       plan->groups.push_back(g);
       gpairs.emplace_back();

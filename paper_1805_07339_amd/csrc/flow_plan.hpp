@@ -37,8 +37,9 @@ struct FlowGroup {
   int32_t w = 0, h = 0;
   std::vector<LevelDim> dims;      // per level
   std::vector<size_t> lvl_off;     // float offset of level l (l >= 1) inside one frame's pyramid slot
-  size_t pyr_floats = 0;           // floats per frame pyramid slot (levels 1..L-1)
-  size_t pair_floats = 0;          // floats per pair scratch (8 planes of level-0 size)
+  size_t pyr_floats = 0;           // floats per frame slot: pyramid levels 1..L-1 (+ Farneback expansion planes)
+  size_t exp_off = 0;              // Farneback: float offset of the 5 expansion planes inside a frame slot
+  size_t pair_floats = 0;          // floats per pair scratch (8 planes of level-0 size; 4 for Farneback)
   size_t extra_pair_bytes = 0;     // additional per-pair scratch (surrogate path)
   int64_t total_pairs = 0;
   std::vector<FlowChunk> chunks;
@@ -51,13 +52,18 @@ struct FlowPlan {
   size_t ws_min = 0;                // smallest workable workspace
   int64_t total_pairs = 0;
   int32_t levels = 0;
+  int32_t solver = 0;               // SCN_SOLVER_*
   std::vector<FlowGroup> groups;
 };
 
 // Per-pair scratch planes (each of level-0 size): coefficient planes a, b, c,
-// the warped second image, and two (u, v) ping-pong buffers.
+// the warped second image, and two (u, v) ping-pong buffers.  Farneback pairs
+// hold only the two (u, v) buffers (planes 0-3); their frames hold the five
+// expansion planes (A11, A22, A12, b1, b2) of the level being solved after
+// the pyramid.
 enum : int32_t { kPlaneA = 0, kPlaneB = 1, kPlaneC = 2, kPlaneW = 3, kPlaneU0 = 4, kPlaneV0 = 5, kPlaneU1 = 6,
                  kPlaneV1 = 7, kPairPlanes = 8 };
+enum : int32_t { kFbPairPlanes = 4, kFbExpPlanes = 5 };
 
 // Build the plan.  flow may be NULL (sizing only).  ws_bytes = 0 plans one
 // chunk per group (that plan's scratch size is ws_needed); otherwise pairs

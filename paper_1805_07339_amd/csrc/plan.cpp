@@ -177,8 +177,22 @@ std::vector<LevelDim> level_dims(int32_t w, int32_t h, int32_t levels) {
 scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
   if (!p) { set_error("flow params are NULL"); return SCN_EINVAL; }
   if (p->levels < 1 || p->levels > 12) { set_error("levels must be in [1, 12]"); return SCN_EINVAL; }
-  if (!(p->alpha > 0.0f) || p->alpha > 1e6f) { set_error("alpha must be in (0, 1e6]"); return SCN_EINVAL; }
   if (p->iters < 0 || p->iters > 100000) { set_error("iters must be in [0, 100000]"); return SCN_EINVAL; }
+  if (p->solver == SCN_SOLVER_FARNEBACK) {
+    if (p->fb_poly_n != 2) { set_error("Farneback: only fb_poly_n = 2 (5x5 expansion) is supported"); return SCN_EUNSUPPORTED; }
+    if (!(p->fb_sigma >= 0.5f && p->fb_sigma <= 8.0f)) { set_error("Farneback: fb_sigma must be in [0.5, 8]"); return SCN_EINVAL; }
+    if (p->fb_win < 0 || p->fb_win > 8) { set_error("Farneback: fb_win must be in [0, 8]"); return SCN_EINVAL; }
+    if (!(p->fb_lambda > 0.0f) || p->fb_lambda > 1e6f) { set_error("Farneback: fb_lambda must be in (0, 1e6]"); return SCN_EINVAL; }
+    if (p->warm_packet >= 2) { set_error("Farneback: the temporal warm start applies to Horn-Schunck only"); return SCN_EINVAL; }
+    if (p->warm_packet < 0) { set_error("warm_packet must be in [0, 2^20]"); return SCN_EINVAL; }
+  } else if (p->solver != SCN_SOLVER_HS) {
+    set_error("solver must be SCN_SOLVER_HS or SCN_SOLVER_FARNEBACK");
+    return SCN_EINVAL;
+  }
+  if (p->solver == SCN_SOLVER_HS && (!(p->alpha > 0.0f) || p->alpha > 1e6f)) {
+    set_error("alpha must be in (0, 1e6]");
+    return SCN_EINVAL;
+  }
   if (p->sweeps_per_pass < 0 || p->sweeps_per_pass > 63) {
     set_error("sweeps_per_pass must be in [0, 63]");
     return SCN_EINVAL;

@@ -254,3 +254,39 @@ def test_window_views_refuse_rows_outside_the_backed_window():
     # the Python wrappers raise before any device work
     with pytest.raises(scn.ScnError):
         scn.count_pairs(scn.Job(t, scn.Sampling.gather([10, 120])))
+
+
+def test_farneback_params_and_workspace():
+    """Farnebäck through scn_flow: the workspace holds two (u, v) buffers per
+    pair and five expansion planes per frame; out-of-range parameters are
+    refused before anything is enqueued."""
+    t = _cpu_table(100, 64, 48)
+    job = scn.Job(t, scn.Sampling.stride(10, 0, 100))
+    L = scn.lib()
+    fb = scn.farneback_params(levels=3)
+    need = scn.workspace_bytes(scn.SCN_OP_FLOW, [job], fb)
+    # 9 pairs x 4 planes + 10 frames x (5 planes + pyramid levels 1, 2)
+    assert need >= 9 * 4 * 64 * 48 * 4 + 10 * (5 * 64 * 48 + 32 * 24 + 16 * 12) * 4
+    arr = scn._jobs_array([job])
+    cases = [(dict(poly_n=3), scn.SCN_EUNSUPPORTED), (dict(sigma=0.4), scn.SCN_EINVAL),
+             (dict(sigma=9.0), scn.SCN_EINVAL), (dict(win=9), scn.SCN_EINVAL), (dict(win=-1), scn.SCN_EINVAL),
+             (dict(lam=0.0), scn.SCN_EINVAL), (dict(lam=float("nan")), scn.SCN_EINVAL),
+             (dict(iters=-1), scn.SCN_EINVAL), (dict(levels=7), scn.SCN_EUNSUPPORTED)]
+    out = torch.zeros(9 * 2 * 64 * 48, dtype=torch.float32)
+    ptrs = (ctypes.c_void_p * 1)(out.data_ptr())
+    ws = torch.zeros(1024, dtype=torch.uint8)
+    for kw, code in cases:
+        bad = scn.farneback_params(**{**dict(levels=3), **kw})
+        assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, arr, 1, ctypes.byref(bad)) == 0, kw
+        assert L.scn_flow(arr, 1, ctypes.byref(bad), ptrs, ws.data_ptr(), 1024, None) == code, kw
+    # the warm start and the surrogate's fallback are Horn-Schunck only
+    warm = scn.farneback_params(levels=3)
+    warm.warm_packet = 4
+    assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, arr, 1, ctypes.byref(warm)) == 0
+    assert "warm" in L.scn_last_error().decode()
+    assert L.scn_workspace_bytes(scn.SCN_OP_SURROGATE, arr, 1, ctypes.byref(fb)) == 0
+    bad_solver = scn.flow_params(levels=3)
+    bad_solver.solver = 2
+    assert L.scn_workspace_bytes(scn.SCN_OP_FLOW, arr, 1, ctypes.byref(bad_solver)) == 0
+    # alpha is a Horn-Schunck parameter: Farnebäck ignores it
+    assert fb.alpha == 0.0 and need > 0
