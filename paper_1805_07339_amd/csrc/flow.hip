@@ -1113,10 +1113,18 @@ scn_status run_fb_chunk(const FlowPlan& plan, const FlowGroup& grp, const FlowCh
       const int32_t mode = it > 0 ? 2 : (result < 0 ? 0 : 1);
       const int32_t dst = (l == 0 && it == prm.iters - 1) ? 2 : (cur < 0 ? 0 : 1 - cur);
       KernelTimer timer("fb_disp", s);
-      const dim3 gd((unsigned)grid), bd(256);
-      if (mode == 0) hipLaunchKernelGGL(k_fb_disp<0>, gd, bd, 0, s, c, g, dp, 0, dst, tiles_x, (int32_t)tpp);
-      else if (mode == 1) hipLaunchKernelGGL(k_fb_disp<1>, gd, bd, 0, s, c, g, dp, cur, dst, tiles_x, (int32_t)tpp);
-      else hipLaunchKernelGGL(k_fb_disp<2>, gd, bd, 0, s, c, g, dp, cur, dst, tiles_x, (int32_t)tpp);
+      const dim3 gd((unsigned)grid), bd(kFdThreads);
+      const int32_t src = mode == 0 ? 0 : cur;
+      switch (mode * 16 + m) {
+#define SCN_FD(md, mm) \
+  case md * 16 + mm: hipLaunchKernelGGL((k_fb_disp<md, mm>), gd, bd, 0, s, c, g, dp, src, dst, tiles_x, (int32_t)tpp); break;
+#define SCN_FD_M(md) SCN_FD(md, 0) SCN_FD(md, 1) SCN_FD(md, 2) SCN_FD(md, 3) SCN_FD(md, 4) SCN_FD(md, 5) \
+  SCN_FD(md, 6) SCN_FD(md, 7) SCN_FD(md, 8)
+        SCN_FD_M(0) SCN_FD_M(1) SCN_FD_M(2)
+#undef SCN_FD_M
+#undef SCN_FD
+        default: set_error("internal: bad Farneback box size"); return SCN_EINVAL;
+      }
       SCN_LAUNCHED("displacement launch");
       cur = dst;
     }
