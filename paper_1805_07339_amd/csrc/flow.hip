@@ -46,7 +46,7 @@ struct LevelGeom {
   int32_t cw, ch;      // coarser level (valid when has_coarse)
   int32_t has_coarse;
   int64_t n0;          // level-0 pixels (plane stride inside a pair's scratch)
-  int64_t lvl_off;     // float offset of this level inside a pyramid slot (l >= 1)
+  int64_t lvl_off;     // float offset of this level inside a pyramid slot (l >= 1; stored as doubles)
   int32_t level;
 };
 
@@ -100,14 +100,12 @@ __device__ __forceinline__ float* plane(const ChunkPtrs& c, int64_t pair, int k,
   return as_global(c.scratch + pair * c.pair_floats + (int64_t)k * n0);
 }
 
-// Image of level l of frame slot f: u8 luma at level 0, float pyramid above.
+// Image of level l of frame slot f: u8 luma at level 0, the exact pyramid
+// (FP64) above.
 struct Img {
   const uint8_t* y8;
-  const float* f;
+  const double* f;
   int64_t pitch;
-  __device__ __forceinline__ float at(int32_t x, int32_t y) const {
-    return y8 ? (float)y8[(int64_t)y * pitch + x] : f[(int64_t)y * pitch + x];
-  }
 };
 __device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const LevelGeom& g) {
   Img im;
@@ -117,7 +115,7 @@ __device__ __forceinline__ Img level_img(const ChunkPtrs& c, int32_t f, const Le
     im.pitch = c.frames[f].pitch;
   } else {
     im.y8 = nullptr;
-    im.f = as_global(c.pyr + (int64_t)f * c.pyr_floats + g.lvl_off);
+    im.f = as_global(reinterpret_cast<const double*>(c.pyr + (int64_t)f * c.pyr_floats + g.lvl_off));
     im.pitch = g.w;
   }
   return im;
@@ -130,13 +128,17 @@ __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi) { r
 // horizontal then vertical, clamp-to-edge.  A workgroup owns 16 x 64 output
 // pixels: it stages the 35 x 131 clamped input pixels in LDS with coalesced
 // loads, forms the horizontal sums of the 35 rows at the 64 even columns, and
-// then the vertical sums, in the same order of operations per pixel as the
-// plain definition (integer sums at level 0, so those are exact).
+// then the vertical sums.  The levels are exact: a level-l value is an integer
+// multiple of 2^-8l below 256 (8 + 8l significant bits), so integer sums at
+// level 0 and FP64 sums above (53-bit significand) round nothing through
+// level 5, and the stored FP64 values equal the plain definition's.  (Levels
+// rounded to FP32 at every step move the flow of ill-conditioned pixels --
+// occlusion edges under large displacements -- by several 1e-3 px.)
 constexpr int kPyrTW = 64, kPyrTH = 16, kPyrIW = 2 * kPyrTW + 3, kPyrIH = 2 * kPyrTH + 3;
 template <bool U8>
 __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, LevelGeom dst, int32_t tiles_x,
                                                   int32_t tiles_per_frame) {
-  using T = typename std::conditional<U8, int, float>::type;
+  using T = typename std::conditional<U8, int, double>::type;
   __shared__ __attribute__((aligned(16))) T sIn[kPyrIH][kPyrIW + 1];
   __shared__ T sH[kPyrIH][kPyrTW];
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, Le
       const int32_t yy = clampi(iy0 + e / kPyrIW, 0, src.h - 1), xx = clampi(ix0 + e % kPyrIW, 0, src.w - 1);
       const uint32_t off = (uint32_t)yy * (uint32_t)im.pitch + (uint32_t)xx;
       if constexpr (U8) v[i] = (int)ldg(im.y8, off);
-      else v[i] = ldg(im.f, 4u * off);
+      else v[i] = ldg(im.f, 8u * off);
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
@@ -198,33 +200,33 @@ __global__ void __launch_bounds__(256) k_pyr_down(ChunkPtrs c, LevelGeom src, Le
       for (int i = 0; i < 5; ++i) hs += ki[i] * sIn[r][2 * x + i];
       sH[r][x] = hs;
     } else {
-      const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
-      float hs = 0.f;
+      const double k[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+      double hs = 0.0;
 #pragma unroll
       for (int i = 0; i < 5; ++i) hs += k[i] * sIn[r][2 * x + i];
       sH[r][x] = hs;
     }
   }
   __syncthreads();
-  float* out = c.pyr + f * c.pyr_floats + dst.lvl_off;
+  double* out = reinterpret_cast<double*>(c.pyr + f * c.pyr_floats + dst.lvl_off);
   for (int e = threadIdx.x; e < kPyrTH * kPyrTW; e += 256) {
     const int ly = e / kPyrTW, x = e % kPyrTW;
     const int32_t gx = ox + x, gy = oy + ly;
     if (gx >= dst.w || gy >= dst.h) continue;
-    float acc;
+    double acc;
     if constexpr (U8) {
       const int ki[5] = {1, 4, 6, 4, 1};
       int s = 0;
 #pragma unroll
       for (int j = 0; j < 5; ++j) s += ki[j] * sH[2 * ly + j][x];
-      acc = (float)s * (1.f / 256.f);
+      acc = (double)s * (1.0 / 256.0);
     } else {
-      const float k[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
-      acc = 0.f;
+      const double k[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+      acc = 0.0;
 #pragma unroll
       for (int j = 0; j < 5; ++j) acc += k[j] * sH[2 * ly + j][x];
     }
-    stg(out, 4u * ((uint32_t)gy * (uint32_t)dst.w + (uint32_t)gx), acc);
+    stg(out, 8u * ((uint32_t)gy * (uint32_t)dst.w + (uint32_t)gx), acc);
   }
 }
 
@@ -237,13 +239,18 @@ constexpr int kSetupTW = 64, kSetupTH = 16;
 // U8: level 0 (luma read as u8 from the table); COARSE: a coarser level
 // exists (start flow from it).  Each thread gathers all of its halo-tile
 // samples into registers before the first LDS store, so the loads of one
-// thread overlap instead of waiting one by one.
+// thread overlap instead of waiting one by one.  Above level 0 the warp, the
+// gradients and the linearised constraint are evaluated in FP64 on the exact
+// pyramid (the coefficients are rounded to FP32 once): at level 0 the u8
+// images are exact and FP32 suffices, while rounding the coarse levels'
+// images and gradients moves ill-conditioned pixels by up to 1e-3 px.
 template <bool U8, bool COARSE, bool INIT, bool LIST>
 __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int32_t coarse_code, int32_t dst_code,
                                                   float alpha2, int32_t tiles_x, int32_t tiles_per_pair) {
+  using T = typename std::conditional<U8, float, double>::type;  // arithmetic of warp and gradients
   constexpr int TW = kSetupTW + 2, NE = (kSetupTH + 2) * TW, IT = (NE + 255) / 256;
-  __shared__ float sT[kSetupTH + 2][kSetupTW + 2];
-  __shared__ float sI[kSetupTH + 2][kSetupTW + 2];
+  __shared__ T sT[kSetupTH + 2][kSetupTW + 2];
+  __shared__ T sI[kSetupTH + 2][kSetupTW + 2];
   __shared__ float sU[kSetupTH][kSetupTW];
   __shared__ float sV[kSetupTH][kSetupTW];
   // A workgroup takes tile `unit` = its index; with an active-pair list (a
@@ -267,8 +274,8 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
     const float* init_v = INIT ? init_u + (int64_t)g.w * g.h : nullptr;
     const uint8_t* y1 = nullptr;
     const uint8_t* y2 = nullptr;
-    const float* f1 = nullptr;
-    const float* f2 = nullptr;
+    const double* f1 = nullptr;
+    const double* f2 = nullptr;
     int64_t p1, p2;
     if constexpr (U8) {
       const FrameDesc d1 = c.frames[pd.f1], d2 = c.frames[pd.f2];
@@ -277,32 +284,33 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
       p1 = d1.pitch;
       p2 = d2.pitch;
     } else {
-      f1 = as_global(c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off);
-      f2 = as_global(c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off);
+      f1 = as_global(reinterpret_cast<const double*>(c.pyr + (int64_t)pd.f1 * c.pyr_floats + g.lvl_off));
+      f2 = as_global(reinterpret_cast<const double*>(c.pyr + (int64_t)pd.f2 * c.pyr_floats + g.lvl_off));
       p1 = p2 = g.w;
     }
     // 32-bit byte offsets (a frame or pyramid level is far below 4 GiB)
     const uint32_t q1 = (uint32_t)p1, q2 = (uint32_t)p2;
     // rows < 2^15 and pitches <= 2^20 (checked on the host): 24-bit products
-    auto at1 = [&](int32_t xx, int32_t yy) -> float {
+    auto at1 = [&](int32_t xx, int32_t yy) -> T {
       if constexpr (U8) return (float)ldg(y1, __umul24((uint32_t)yy, q1) + (uint32_t)xx);
-      else return ldg(f1, 4u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
+      else return ldg(f1, 8u * (__umul24((uint32_t)yy, q1) + (uint32_t)xx));
     };
     // Warped I2 at (X, Y) = (xi + xf, yi + yf), X given as integer + fraction
     // (exact far from the origin), clamped bilinear: outside [0, w-2] the x
     // fraction is 0 at the clamped column (likewise in y).  The two columns of
     // a row are read by one load (2 bytes at level 0, 8 bytes above; unaligned
-    // global loads are allowed) at xs = clamp(xi, 0, w - 2); past the right
-    // edge the clamped sample is the second element with weight 1, which is
-    // the same value as the clamped column with weight 0.
-    auto warp_sample = [&](int32_t xi, float xf, int32_t yi, float yf) -> float {
+    // global loads are allowed; 16-byte pairs of doubles above level 0) at
+    // xs = clamp(xi, 0, w - 2); past the right edge the clamped sample is the
+    // second element with weight 1, which is the same value as the clamped
+    // column with weight 0.
+    auto warp_sample = [&](int32_t xi, float xf, int32_t yi, float yf) -> T {
       int32_t xs;
-      float fx;
+      T fx;
       if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= g.w - 1) { xs = g.w - 2; fx = 1.f; } else { xs = xi; fx = xf; }
       const bool iny = (uint32_t)yi < (uint32_t)(g.h - 1);
       const int32_t y0 = clampi(yi, 0, g.h - 1), y1 = y0 + (iny ? 1 : 0);
-      const float fy = iny ? yf : 0.f;
-      float a0, b0, a1, b1;
+      const T fy = iny ? yf : 0.f;
+      T a0, b0, a1, b1;
       if constexpr (U8) {
         const uint32_t w0 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y0, q2) + (uint32_t)xs);
         const uint32_t w1 = ldg(reinterpret_cast<const uint16_t*>(y2), __umul24((uint32_t)y1, q2) + (uint32_t)xs);
@@ -311,17 +319,18 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
         a1 = (float)(w1 & 0xFFu);
         b1 = (float)(w1 >> 8);
       } else {
-        typedef float f2v __attribute__((ext_vector_type(2)));
-        const f2v r0 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y0, q2) + (uint32_t)xs));
-        const f2v r1 = ldg(reinterpret_cast<const f2v*>(f2), 4u * (__umul24((uint32_t)y1, q2) + (uint32_t)xs));
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v r0 = ldg(reinterpret_cast<const d2v*>(f2), 8u * (__umul24((uint32_t)y0, q2) + (uint32_t)xs));
+        const d2v r1 = ldg(reinterpret_cast<const d2v*>(f2), 8u * (__umul24((uint32_t)y1, q2) + (uint32_t)xs));
         a0 = r0.x;
         b0 = r0.y;
         a1 = r1.x;
         b1 = r1.y;
       }
-      const float top = (1.f - fx) * a0 + fx * b0;
-      const float bot = (1.f - fx) * a1 + fx * b1;
-      return (1.f - fy) * top + fy * bot;
+      const T one = 1;
+      const T top = (one - fx) * a0 + fx * b0;
+      const T bot = (one - fx) * a1 + fx * b1;
+      return (one - fy) * top + fy * bot;
     };
     // Start flow = 2 * bilinear(coarse flow, x/2, y/2), separably: the
     // horizontal interpolation of the coarse rows under the tile ((oy-1)/2 ..
@@ -366,7 +375,8 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
       }
       __syncthreads();
     }
-    float rT[IT], rI[IT], rU[IT], rV[IT];
+    T rT[IT], rI[IT];
+    float rU[IT], rV[IT];
     // halo element e = tid + 256 i at (ty, tx) = (e / TW, e % TW), advanced
     // incrementally (256 = 3 TW + 58); elements past the tile repeat the last
     int hty = (int)threadIdx.x / TW, htx = (int)threadIdx.x % TW;
@@ -435,16 +445,18 @@ __global__ void __launch_bounds__(256) k_hs_setup(ChunkPtrs c, LevelGeom g, int3
       // Ix = (central difference of I1 + that of T) / 2 with each difference
       // halved: the two power-of-two scalings are folded into one factor 1/4
       // (exact: scaling by 2^-k commutes with rounding for these magnitudes)
-      const float Ix = ((sI[hy][xr] - sI[hy][xl]) + (sT[hy][xr] - sT[hy][xl])) * 0.25f;
-      const float Iy = ((sI[yd][hx] - sI[yu][hx]) + (sT[yd][hx] - sT[yu][hx])) * 0.25f;
-      const float It = sT[hy][hx] - sI[hy][hx];
-      const float Itp = It - Ix * u0 - Iy * v0;
-      const float den = alpha2 + Ix * Ix + Iy * Iy;
-      const float r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
+      const T Ix = ((sI[hy][xr] - sI[hy][xl]) + (sT[hy][xr] - sT[hy][xl])) * (T)0.25;
+      const T Iy = ((sI[yd][hx] - sI[yu][hx]) + (sT[yd][hx] - sT[yu][hx])) * (T)0.25;
+      const T It = sT[hy][hx] - sI[hy][hx];
+      const T Itp = It - Ix * (T)u0 - Iy * (T)v0;
+      const T den = (T)alpha2 + Ix * Ix + Iy * Iy;
+      T r;
+      if constexpr (U8) r = rsqrtf(den);  // within a few ulps; den >= alpha^2 > 0
+      else r = 1.0 / sqrt(den);
       const uint32_t p4 = 4u * (__umul24((uint32_t)y, (uint32_t)g.w) + (uint32_t)x);
-      stg(pa, p4, Ix * r);
-      stg(pb, p4, Iy * r);
-      stg(pc, p4, Itp * r);
+      stg(pa, p4, (float)(Ix * r));
+      stg(pb, p4, (float)(Iy * r));
+      stg(pc, p4, (float)(Itp * r));
       stg(dst, p4, u0);
       stg(dst, p4 + 4u * (uint32_t)n, v0);
     }

@@ -73,9 +73,9 @@ scn_status build_flow_plan(const scn_job* jobs, int32_t n_jobs, const scn_flow_p
       g.dims = level_dims(t.width, t.height, p->levels);
       g.lvl_off.assign(p->levels, 0);
       size_t off = 0;
-      for (int32_t l = 1; l < p->levels; ++l) {
+      for (int32_t l = 1; l < p->levels; ++l) {  // levels >= 1 are FP64: two floats per pixel
         g.lvl_off[l] = off;
-        off += (size_t)g.dims[l].w * g.dims[l].h;
+        off += (size_t)2 * g.dims[l].w * g.dims[l].h;
       }
       const size_t n0 = (size_t)t.width * t.height;
       g.exp_off = off;

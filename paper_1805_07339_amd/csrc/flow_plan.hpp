@@ -36,7 +36,7 @@ struct FlowChunk {
 struct FlowGroup {
   int32_t w = 0, h = 0;
   std::vector<LevelDim> dims;      // per level
-  std::vector<size_t> lvl_off;     // float offset of level l (l >= 1) inside one frame's pyramid slot
+  std::vector<size_t> lvl_off;     // float offset of level l (l >= 1, FP64 values) inside one frame's slot
   size_t pyr_floats = 0;           // floats per frame slot: pyramid levels 1..L-1 (+ Farneback expansion planes)
   size_t exp_off = 0;              // Farneback: float offset of the 5 expansion planes inside a frame slot
   size_t pair_floats = 0;          // floats per pair scratch (8 planes of level-0 size; 4 for Farneback)

@@ -78,14 +78,13 @@ def test_camera_rig_2048_five_levels():
     d, q = float(e.max()), float(np.quantile(e, 0.9999))
     print("rig 2048^2 L=5 max |d| = %.3g, 99.99th percentile %.3g, > 1e-3: %d px" % (d, q, int((e > TOL).sum())),
           flush=True)
-    # This pair is worse conditioned than the 1080p ones: 5 levels, up to
-    # 64 px of disparity across the rig and hard occlusion edges.  The
-    # oracle's own steps evaluated in FP32 differ from its FP64 result by up
-    # to 7.4e-3 px on about 200 of the 4.2M pixels (5e-5 of them), so FP32
-    # cannot meet 1e-3 px everywhere here: the bound is 1e-2 px on every
-    # pixel and 1e-3 px at the 99.99th percentile.
-    assert d <= 1e-2
-    assert q <= TOL
+    # This pair is worse conditioned than the 1080p ones (5 levels, up to 64
+    # px of disparity across the rig, hard occlusion edges): a pyramid
+    # rounded to FP32 at every step moves some pixels by 4e-3 px.  The
+    # kernels keep the pyramid exact and evaluate the coarse levels' setup in
+    # FP64 (tests/fp_budget.py measures each step's share), so the contract's
+    # 1e-3 px holds on every pixel.
+    assert d <= TOL
     # disparity direction: the content moves right from camera c to c+1
     inner = f[1, 0, 256:-256, 256:-256]
     assert float(inner.mean()) > 0.0
