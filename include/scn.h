@@ -316,6 +316,19 @@ scn_status scn_adam_step(float* master, float* m, float* v, const float* grads, 
 scn_status scn_surrogate_grads(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* targets,
                                float* grads, float* loss, void* ws, size_t ws_bytes, scn_stream_t stream);
 
+/* One training step (the trainer's inner loop as one call): the loss and
+ * gradients of the batch exactly as scn_surrogate_grads, then the Adam step
+ * exactly as scn_adam_step with step number `step` and learning rate `lr`,
+ * which updates master, m and v and repacks `net`.  grads: device,
+ * scn_net_params() floats of scratch (overwritten with the batch's
+ * gradients); loss: device, 1 float.  Arguments of both parts are validated
+ * before anything is enqueued.  ws: scn_workspace_bytes(
+ * SCN_OP_SURROGATE_GRADS, ...) bytes. */
+scn_status scn_surrogate_train_step(const scn_job* jobs, int32_t n_jobs, float* const* targets, float* master,
+                                    float* m, float* v, float* grads, void* net, int32_t step, float lr, float beta1,
+                                    float beta2, float eps, float* loss, void* ws, size_t ws_bytes,
+                                    scn_stream_t stream);
+
 /* The network's full-resolution flow for every pair (no gate, no fallback).
  * flow[j]: device, float [P_j][2][H][W]. */
 scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* flow, void* ws,

@@ -63,7 +63,8 @@ class CFlowParams(ctypes.Structure):
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
            "scn_hist_diff", "scn_space_map", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
            "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
-           "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate", "scn_hist_static"]
+           "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate", "scn_hist_static",
+           "scn_surrogate_train_step"]
 
 _lib = None
 
@@ -121,6 +122,10 @@ def lib() -> ctypes.CDLL:
     L.scn_adam_step.restype = ctypes.c_int
     L.scn_surrogate_grads.argtypes = [P(CJob), ctypes.c_int32, vp, P(vp), vp, vp, vp, ctypes.c_size_t, vp]
     L.scn_surrogate_grads.restype = ctypes.c_int
+    L.scn_surrogate_train_step.argtypes = [P(CJob), ctypes.c_int32, P(vp), vp, vp, vp, vp, vp, ctypes.c_int32,
+                                           ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp,
+                                           ctypes.c_size_t, vp]
+    L.scn_surrogate_train_step.restype = ctypes.c_int
     L.scn_surrogate_infer.argtypes = [P(CJob), ctypes.c_int32, vp, P(vp), vp, ctypes.c_size_t, vp]
     L.scn_surrogate_infer.restype = ctypes.c_int
     L.scn_flow_surrogate.argtypes = [P(CJob), ctypes.c_int32, P(CFlowParams), vp, ctypes.c_float, P(vp), P(vp), P(vp),
@@ -471,6 +476,24 @@ def surrogate_grads(jobs: Sequence[Job], net: torch.Tensor, targets: List[torch.
         ws = _ws(dev, workspace_bytes(SCN_OP_SURROGATE_GRADS, jobs), "surrogate")
     _check(lib().scn_surrogate_grads(_jobs_array(jobs), len(jobs), net.data_ptr(), _ptr_array(targets),
                                      grads.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return grads, loss
+
+
+def surrogate_train_step(jobs: Sequence[Job], targets: List[torch.Tensor], master, m, v, net, step: int, lr: float,
+                         beta1=0.9, beta2=0.999, eps=1e-8, grads: Optional[torch.Tensor] = None,
+                         loss: Optional[torch.Tensor] = None, stream=None, ws: Optional[torch.Tensor] = None):
+    """Gradients of the batch and the Adam step in one call; returns (grads, loss)."""
+    dev = net.device
+    if grads is None:
+        grads = torch.empty(net_params(), dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = _ws(dev, workspace_bytes(SCN_OP_SURROGATE_GRADS, jobs), "surrogate")
+    _check(lib().scn_surrogate_train_step(_jobs_array(jobs), len(jobs), _ptr_array(targets), master.data_ptr(),
+                                          m.data_ptr(), v.data_ptr(), grads.data_ptr(), net.data_ptr(), step, lr,
+                                          beta1, beta2, eps, loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                          _stream(stream)))
     return grads, loss
 
 

@@ -616,129 +616,144 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
 }
 
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
-// kernel.  A workgroup owns TOH x TOW conv2 outputs; it stages the net-input
-// tile (2 channels, zero outside the image), computes the conv1 outputs that
+// persistent kernel.  A workgroup stages conv2's weights (36 KB) in LDS once
+// and then walks conv2 output tiles t, t + gridDim.x, ...  Per tile (TOH x TOW
+// conv2 outputs) it forms the network-input tile (2 channels, zero outside
+// the image) from the two frames' luma, computes the conv1 outputs that
 // conv2's input tile needs straight into LDS (zero outside the image, which
-// is conv2's padding), and runs conv2 from there.  conv1's activation never
-// reaches HBM (the unfused pair writes and re-reads it: 64 B per half-res
-// pixel).  conv1 uses the same fragments, MFMA and rounding as k_conv_fwd<0>,
-// so the conv2 input is bitwise the same.
-template <int TOH, int TOW, int NWAVE, bool BLDS>
+// is conv2's padding), and runs conv2 from the LDS tile and weights.  conv1's
+// activation never reaches HBM (the unfused pair writes and re-reads it: 64 B
+// per half-res pixel).  The next tile's luma loads are issued before the
+// current tile's conv2 MFMAs and land in the other network-input buffer after
+// them.  conv1 uses the same fragments, MFMA and rounding as k_conv_fwd<0>,
+// so the conv2 input is bitwise the same.  4 x 64 tiles with 8 waves run 15%
+// faster than 4 x 32 (one fewer tile per 256 outputs re-stages half as many
+// halo pixels per output); one workgroup per CU (the LDS holds 138 KB).
+template <int TOH, int TOW, int NWAVE>
 __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restrict__ frames,
-                                                       const PairDesc* __restrict__ pairs,
-                                                       const uint8_t* __restrict__ blob, bf16_t* __restrict__ y,
-                                                       CGeom g1, CGeom g2, int32_t tiles_x, int32_t tiles_per_img) {
+                                                        const PairDesc* __restrict__ pairs,
+                                                        const uint8_t* __restrict__ blob, bf16_t* __restrict__ y,
+                                                        CGeom g1, CGeom g2, int32_t tiles_x, int32_t tiles_per_img,
+                                                        int32_t n_tiles) {
   constexpr int IH = 2 * TOH + 1, IW = 2 * TOW + 1, CP = 32 + 8;  // conv2 input tile = conv1 outputs
   constexpr int XH = IH + 2, XW = IW + 2;                          // net-input tile
   constexpr int NT = 64 * NWAVE;
   static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].stride == 2, "layer shapes");
-  constexpr int W2 = BLDS ? 9 * 64 * 32 : 8;  // conv2's forward weights [tap][co][ci]
-  __shared__ uint32_t xt[XH * XW];  // two bf16 channels per pixel
+  constexpr int W2 = 9 * 64 * 32;  // conv2's forward weights [tap][co][ci]
+  __shared__ uint32_t xt[2][XH * XW];  // two bf16 channels per pixel, double-buffered
   __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
   __shared__ __attribute__((aligned(16))) bf16_t wlds[W2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int n = blk / tiles_per_img;
-  const int t = blk % tiles_per_img;
-  const int oy0 = (t / tiles_x) * TOH, ox0 = (t % tiles_x) * TOW;
-  const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
-  const int xy0 = cy0 - 1, xx0 = cx0 - 1;          // net-input coordinates of xt (0, 0)
-
-  // The network input is formed here from the two frames' luma (the same
-  // arithmetic as k_net_input): per half-resolution pixel the 2x2 mean
-  // (round half up) as (v - 128) / 64 in BF16, channel 0 = first frame.
   constexpr int NX = XH * XW, ITX = (NX + NT - 1) / NT;
-  const PairDesc pd = pairs[n];
-  const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
-  const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
   uint32_t xr[ITX];
+  // network input of tile t into xr: per half-resolution pixel the 2x2 luma
+  // mean (round half up) as (v - 128) / 64 in BF16, channel 0 = first frame
+  // (the arithmetic of k_net_input); (v - 128) / 64 with integer v is exact
+  // in BF16, so the hardware pack returns the same bits
+  auto load_x = [&](int t) {
+    const int n = t / tiles_per_img, r = t % tiles_per_img;
+    const int xy0 = 2 * (r / tiles_x) * TOH - 2, xx0 = 2 * (r % tiles_x) * TOW - 2;
+    const PairDesc pd = pairs[n];
+    const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
+    const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
 #pragma unroll
-  for (int i = 0; i < ITX; ++i) {
-    const int e = min(tid + i * NT, NX - 1);
-    const int yy = xy0 + e / XW, xx = xx0 + e % XW;
-    const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
-    const uint32_t ry = 2u * (uint32_t)(ok ? yy : 0), rx = 2u * (uint32_t)(ok ? xx : 0);
-    // 2x2 luma sums; the two bytes of a row come from one 2-byte load
-    auto sum4 = [&](const uint8_t* yp, uint32_t pitch) -> int {
-      const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(yp), ry * pitch + rx);
-      const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(yp), (ry + 1) * pitch + rx);
-      return (int)((w0 & 0xFFu) + (w0 >> 8) + (w1 & 0xFFu) + (w1 >> 8));
-    };
-    const int s1 = sum4(fa.y, pa), s2 = sum4(fb.y, pbp);
-    // (v - 128) / 64 with integer v is exact in BF16: the hardware pack
-    // returns the same bits as f2bf
-    const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
-                                   (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
-    xr[i] = ok ? v : 0u;
-  }
+    for (int i = 0; i < ITX; ++i) {
+      const int e = min(tid + i * NT, NX - 1);
+      const int yy = xy0 + e / XW, xx = xx0 + e % XW;
+      const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
+      const uint32_t ry = 2u * (uint32_t)(ok ? yy : 0), rx = 2u * (uint32_t)(ok ? xx : 0);
+      auto sum4 = [&](const uint8_t* yp, uint32_t pitch) -> int {
+        const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(yp), ry * pitch + rx);
+        const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(yp), (ry + 1) * pitch + rx);
+        return (int)((w0 & 0xFFu) + (w0 >> 8) + (w1 & 0xFFu) + (w1 >> 8));
+      };
+      const int s1 = sum4(fa.y, pa), s2 = sum4(fb.y, pbp);
+      const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
+                                     (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
+      xr[i] = ok ? v : 0u;
+    }
+  };
+  auto store_x = [&](uint32_t* buf) {
+#pragma unroll
+    for (int i = 0; i < ITX; ++i)
+      if (tid + i * NT < NX) buf[tid + i * NT] = xr[i];
+  };
+  int t = xcd_block(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;  // uniform over the workgroup, before any barrier
   const bf16_t* wf1 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(0));
   const float* b1 = reinterpret_cast<const float*>(blob + blob_bias_off(0));
+  const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
   bf16x8 bw[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) bw[nb] = ld8(wf1 + (nb * 16 + r16) * 32 + kg * 8);
-  constexpr int NW8 = BLDS ? W2 / 8 : 0, WIT = (NW8 + NT - 1) / NT;
-  const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(1));
-  uint4 wreg[WIT > 0 ? WIT : 1];
+  f32x4 bv[2];
 #pragma unroll
-  for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
+  for (int nb = 0; nb < 2; ++nb) bv[nb] = bias4(b1, nb * 16 + 4 * kg);
+  {
+    constexpr int NW8 = W2 / 8, WIT = (NW8 + NT - 1) / NT;
+    const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(1));
+    uint4 wreg[WIT];
 #pragma unroll
-  for (int i = 0; i < ITX; ++i)
-    if (tid + i * NT < NX) xt[tid + i * NT] = xr[i];
+    for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
+    load_x(t);
 #pragma unroll
-  for (int i = 0; i < WIT; ++i) {
-    const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r (conv2: CI = 32)
-    if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<32>::off(c / 4, c % 4)) = wreg[i];
+    for (int i = 0; i < WIT; ++i) {
+      const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r (conv2: CI = 32)
+      if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<32>::off(c / 4, c % 4)) = wreg[i];
+    }
+    store_x(xt[0]);
   }
   __syncthreads();
-
   // per lane: the xt offsets of its four taps (lane group kg covers taps
-  // 4kg .. 4kg+3 of K = 18 = 9 taps x 2 channels; taps >= 9 are zero) and
-  // the biases of its output channels
+  // 4kg .. 4kg+3 of K = 18 = 9 taps x 2 channels; taps >= 9 are zero)
   int toff[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int tap = 4 * kg + j;
     toff[j] = tap < 9 ? (tap / 3) * XW + tap % 3 : -1;
   }
-  f32x4 bv[2];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) bv[nb] = bias4(b1, nb * 16 + 4 * kg);
   constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16, NIT = (NBK + NWAVE - 1) / NWAVE;
-  // unrolled: the LDS reads and MFMAs of successive pixel blocks overlap
+  for (int buf = 0; t < n_tiles; t += gridDim.x, buf ^= 1) {
+    const int n = t / tiles_per_img, r = t % tiles_per_img;
+    const int oy0 = (r / tiles_x) * TOH, ox0 = (r % tiles_x) * TOW;
+    const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
+    const uint32_t* xb = xt[buf];
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int blk = wv + it * NWAVE;
-    if (blk >= NBK) break;
-    const int pidx = blk * 16 + r16;
-    const int pi = min(pidx, NPX - 1);
-    const int py = pi / IW, px = pi % IW;
-    // each xt word is a tap's two channels already packed (channel 0 low)
-    uint4 pw;
-    const int pb = py * XW + px;
-    pw.x = toff[0] >= 0 ? xt[pb + toff[0]] : 0u;
-    pw.y = toff[1] >= 0 ? xt[pb + toff[1]] : 0u;
-    pw.z = toff[2] >= 0 ? xt[pb + toff[2]] : 0u;
-    pw.w = toff[3] >= 0 ? xt[pb + toff[3]] : 0u;
-    const bf16x8 a = __builtin_bit_cast(bf16x8, pw);
-    const int cy = cy0 + py, cx = cx0 + px;
-    const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
+    for (int it = 0; it < NIT; ++it) {
+      const int blk = wv + it * NWAVE;
+      if (blk >= NBK) break;
+      const int pidx = blk * 16 + r16;
+      const int pi = min(pidx, NPX - 1);
+      const int py = pi / IW, px = pi % IW;
+      uint4 pw;
+      const int pb = py * XW + px;
+      pw.x = toff[0] >= 0 ? xb[pb + toff[0]] : 0u;
+      pw.y = toff[1] >= 0 ? xb[pb + toff[1]] : 0u;
+      pw.z = toff[2] >= 0 ? xb[pb + toff[2]] : 0u;
+      pw.w = toff[3] >= 0 ? xb[pb + toff[3]] : 0u;
+      const bf16x8 a = __builtin_bit_cast(bf16x8, pw);
+      const int cy = cy0 + py, cx = cx0 + px;
+      const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const f32x4 acc = mfma(bw[nb], a, bv[nb]);  // bias as the accumulator's start, as in k_conv_fwd<0>
-      const int co = nb * 16 + 4 * kg;
-      uint2 pk = make_uint2(0u, 0u);
-      if (inside) {
-        pk.x = relu_bf16x2(pack_bf16x2(acc[0], acc[1]));
-        pk.y = relu_bf16x2(pack_bf16x2(acc[2], acc[3]));
+      for (int nb = 0; nb < 2; ++nb) {
+        const f32x4 acc = mfma(bw[nb], a, bv[nb]);
+        const int co = nb * 16 + 4 * kg;
+        uint2 pk = make_uint2(0u, 0u);
+        if (inside) {
+          pk.x = relu_bf16x2(pack_bf16x2(acc[0], acc[1]));
+          pk.y = relu_bf16x2(pack_bf16x2(acc[2], acc[3]));
+        }
+        if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
       }
-      if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
     }
+    __syncthreads();
+    const int tn = t + gridDim.x;
+    if (tn < n_tiles) load_x(tn);  // in flight during this tile's conv2 MFMAs
+    conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, true>(tile, wlds, b2, y, g2, n, oy0, ox0);
+    if (tn < n_tiles) store_x(xt[buf ^ 1]);  // that buffer was last read before the barrier above
+    __syncthreads();  // the next tile's conv1 overwrites the tile conv2 just read
   }
-  __syncthreads();
-  const bf16_t* wf2 = BLDS ? wlds : reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
-  const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
-  conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, BLDS>(tile, wf2, b2, y, g2, n, oy0, ox0);
 }
 
 // ---------------------------------------------------------------------------
@@ -870,76 +885,189 @@ __global__ void k_dx_post(const float* __restrict__ dxe, const bf16_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient, split over pixel chunks (deterministic):
+// weight gradient, split over chunks of whole output rows (deterministic):
 //   part[chunk][tap][co][ci] = sum_{m in chunk} dy[m][co] x_e(m, tap)[ci]
-//   partb[chunk][co] = sum_{m in chunk} dy[m][co]  (tap-0 workgroups)
-// Each step stages 32 pixels of dy and of the tap's input, transposed to
-// [channel][pixel] in LDS, so that 8 consecutive pixels of one channel are a
-// 16-byte MFMA fragment.
-template <int L>
-__global__ void __launch_bounds__(256) k_conv_dw(const void* __restrict__ dy, const bf16_t* __restrict__ x,
-                                                 float* __restrict__ part, float* __restrict__ partb, CGeom g,
-                                                 int32_t chunk_px) {
+//   partb[chunk][co] = sum_{m in chunk} dy[m][co]
+// A workgroup computes the taps of TR tap rows of one chunk (all nine, or
+// one tap row for the two layers with 64 x 96 channel pairs, whose
+// accumulators would not fit otherwise).  It walks steps of 32
+// output pixels of one row; per step dy and the nine taps' inputs are staged
+// transposed to [channel][pixel] in LDS (8 consecutive pixels of a channel
+// are one 16-byte MFMA fragment, K = pixels): 16-byte loads of 8 channels of
+// 8 pixels are transposed in registers with byte permutes and stored as 8
+// 16-byte rows.  The next step's loads are in flight during this step's
+// MFMAs.  conv1's 2-channel input and conv6's FP32 2-channel dy are staged
+// element-wise (their other channel rows stay zero).
+constexpr int64_t kDwMaxChunks = 512;  // weight-gradient workgroups per layer (at most)
+inline int64_t dw_rows_per_chunk(int64_t rows) { return std::max<int64_t>(1, (rows + kDwMaxChunks - 1) / kDwMaxChunks); }
+inline int64_t dw_chunks(int64_t rows) { return (rows + dw_rows_per_chunk(rows) - 1) / dw_rows_per_chunk(rows); }
+
+// 8 x 8 transpose of 16-bit elements: in[j] holds channels 0..7 of pixel j,
+// out[c] receives pixels 0..7 of channel c.
+__device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[8]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;  // high or low halves of the two dwords
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint4 a = in[2 * k], b = in[2 * k + 1];
+      const uint32_t da = (c >> 1) == 0 ? a.x : (c >> 1) == 1 ? a.y : (c >> 1) == 2 ? a.z : a.w;
+      const uint32_t db = (c >> 1) == 0 ? b.x : (c >> 1) == 1 ? b.y : (c >> 1) == 2 ? b.z : b.w;
+      w[k] = __builtin_amdgcn_perm(db, da, sel);  // low 16 bits from pixel 2k, high 16 bits from pixel 2k + 1
+    }
+    out[c] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <int L, int NW, int TR>
+__global__ void __launch_bounds__(64 * NW) k_conv_dw(const void* __restrict__ dy, const bf16_t* __restrict__ x,
+                                                     float* __restrict__ part, float* __restrict__ partb, CGeom g,
+                                                     int32_t rows_per_chunk) {
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), CIP = cpad(CI);
   constexpr bool UP = D.up != 0;
-  constexpr int TCO = COP / 16, TCI = CIP / 16, NT = TCO * TCI, TPW = (NT + 3) / 4;
-  __shared__ __attribute__((aligned(16))) bf16_t sdy[COP][40];
-  __shared__ __attribute__((aligned(16))) bf16_t sx[CIP][40];
-  const int tap = blockIdx.x % 9;
-  const int64_t chunk = blockIdx.x / 9;
-  const int ky = tap / 3, kx = tap % 3;
+  constexpr bool DY32 = L == kLayers - 1;  // conv6: dy is the FP32 gradient of the 2-channel flow
+  constexpr bool XS = CI < 8;              // conv1: 2 input channels
+  static_assert(DY32 ? CO == 2 : CO % 8 == 0, "dy staging");
+  static_assert(XS ? CI == 2 : CI % 8 == 0, "input staging");
+  constexpr int NT = 64 * NW, LS = 40;  // staged rows: 32 pixels + padding (80-byte rows)
+  constexpr int NTAP = 3 * TR;  // taps of this workgroup: tap rows ky0 .. ky0 + TR - 1
+  constexpr int TCO = COP / 16, TCI = CIP / 16, NTILE = NTAP * TCO * TCI, TPW = (NTILE + NW - 1) / NW;
+  // staging units of a step: dy (8 x 8 blocks, or one pixel for DY32) then x
+  // (tap x 8 x 8 blocks, or tap x one pixel for XS)
+  constexpr int NDY = DY32 ? 32 : 4 * (CO / 8);
+  constexpr int NXU = XS ? NTAP * 32 : NTAP * 4 * (CI / 8);
+  constexpr int NU = NDY + NXU, UPT = (NU + NT - 1) / NT;
+  __shared__ __attribute__((aligned(16))) bf16_t sdy[COP][LS];
+  __shared__ __attribute__((aligned(16))) bf16_t sx[NTAP][CIP][LS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const int64_t M = (int64_t)g.n * g.ho * g.wo;
-  const int64_t m0 = chunk * chunk_px, m1 = min(M, m0 + chunk_px);
+  const int64_t rows = (int64_t)g.n * g.ho;
+  const int64_t chunk = blockIdx.x / (3 / TR);
+  const int ky0 = (int)(blockIdx.x % (3 / TR)) * TR;
+  const int64_t r0 = chunk * rows_per_chunk, r1 = min(rows, r0 + rows_per_chunk);
+  const int nxb = (g.wo + 31) / 32;
+  const int nsteps = (int)(r1 - r0) * nxb;
+  // channel rows no unit writes (padding of 2-channel operands) stay zero
+  if constexpr (DY32)
+    for (int e = tid; e < (COP - CO) * LS; e += NT) sdy[CO + e / LS][e % LS] = 0;
+  if constexpr (XS)
+    for (int e = tid; e < NTAP * (CIP - CI) * LS; e += NT) {
+      const int t = e / ((CIP - CI) * LS), rem = e % ((CIP - CI) * LS);
+      sx[t][CI + rem / LS][rem % LS] = 0;
+    }
+
+  uint4 ureg[UPT][8];  // loaded units (element-wise units use the first words)
+  auto load = [&](int st) {
+    const int64_t r = r0 + st / nxb;
+    const int xb = st % nxb;
+    const int n = (int)(r / g.ho), oy = (int)(r % g.ho);
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int u = tid + k * NT;
+      if (u >= NU) continue;
+      if (u < NDY) {
+        if constexpr (DY32) {
+          const int ox = xb * 32 + u;
+          float2 v = make_float2(0.f, 0.f);
+          if (ox < g.wo)
+            v = reinterpret_cast<const float2*>(dy)[((int64_t)n * g.ho + oy) * g.wo + ox];
+          ureg[k][0] = make_uint4(f2bf(v.x), f2bf(v.y), 0, 0);
+        } else {
+          const int pg = u / (CO / 8), cg = u % (CO / 8);
+          const bf16_t* base = reinterpret_cast<const bf16_t*>(dy) + (((int64_t)n * g.ho + oy) * g.wo) * CO + 8 * cg;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int ox = xb * 32 + 8 * pg + j;
+            ureg[k][j] = ox < g.wo ? *reinterpret_cast<const uint4*>(base + (int64_t)ox * CO) : make_uint4(0, 0, 0, 0);
+          }
+        }
+      } else {
+        const int v = u - NDY;
+        if constexpr (XS) {
+          const int tap = v / 32, p = v % 32, ky = ky0 + tap / 3, kx = tap % 3;
+          const int ox = xb * 32 + p;
+          const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
+          uint32_t w = 0;
+          if (ox < g.wo && iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
+            const int sy = UP ? iy >> 1 : iy, sxx = UP ? ix >> 1 : ix;
+            w = *reinterpret_cast<const uint32_t*>(x + (((int64_t)n * g.hi + sy) * g.wi + sxx) * CI);
+          }
+          ureg[k][0] = make_uint4(w, 0, 0, 0);
+        } else {
+          const int tap = v / (4 * (CI / 8)), rem = v % (4 * (CI / 8));
+          const int pg = rem / (CI / 8), cg = rem % (CI / 8), ky = ky0 + tap / 3, kx = tap % 3;
+          const int iy = oy * S + ky - 1;
+          const bool row_in = iy >= 0 && iy < g.he;
+          const int sy = UP ? iy >> 1 : iy;
+          const bf16_t* base = x + ((int64_t)n * g.hi + (row_in ? sy : 0)) * g.wi * CI + 8 * cg;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int ox = xb * 32 + 8 * pg + j, ix = ox * S + kx - 1;
+            const bool ok = row_in && ox < g.wo && ix >= 0 && ix < g.we;
+            const int sxx = UP ? ix >> 1 : ix;
+            ureg[k][j] = ok ? *reinterpret_cast<const uint4*>(base + (int64_t)sxx * CI) : make_uint4(0, 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int u = tid + k * NT;
+      if (u >= NU) continue;
+      if (u < NDY) {
+        if constexpr (DY32) {
+          sdy[0][u] = (bf16_t)ureg[k][0].x;
+          sdy[1][u] = (bf16_t)ureg[k][0].y;
+        } else {
+          const int pg = u / (CO / 8), cg = u % (CO / 8);
+          uint4 t8[8];
+          transpose8x8(ureg[k], t8);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4*>(&sdy[8 * cg + c][8 * pg]) = t8[c];
+        }
+      } else {
+        const int v = u - NDY;
+        if constexpr (XS) {
+          const int tap = v / 32, p = v % 32;
+          sx[tap][0][p] = (bf16_t)(ureg[k][0].x & 0xFFFFu);
+          sx[tap][1][p] = (bf16_t)(ureg[k][0].x >> 16);
+        } else {
+          const int tap = v / (4 * (CI / 8)), rem = v % (4 * (CI / 8));
+          const int pg = rem / (CI / 8), cg = rem % (CI / 8);
+          uint4 t8[8];
+          transpose8x8(ureg[k], t8);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4*>(&sx[tap][8 * cg + c][8 * pg]) = t8[c];
+        }
+      }
+    }
+  };
+
   f32x4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
-  for (int64_t ms = m0; ms < m1; ms += 32) {
-    // stage dy: 32 pixels x COP channels
-    for (int e = tid; e < 32 * COP; e += 256) {
-      const int p = e / COP, c = e % COP;
-      const int64_t m = ms + p;
-      float v = 0.f;
-      if (m < m1 && c < CO) {
-        if constexpr (L == kLayers - 1)
-          v = reinterpret_cast<const float*>(dy)[m * CO + c];
-        else
-          v = bf2f(reinterpret_cast<const bf16_t*>(dy)[m * CO + c]);
-      }
-      sdy[c][p] = f2bf(v);
-    }
-    // stage the tap's input: 32 pixels x CIP channels
-    for (int e = tid; e < 32 * CIP; e += 256) {
-      const int p = e / CIP, c = e % CIP;
-      const int64_t m = ms + p;
-      bf16_t v = 0;
-      if (m < m1 && c < CI) {
-        const int ox = (int)(m % g.wo);
-        const int64_t t = m / g.wo;
-        const int oy = (int)(t % g.ho);
-        const int64_t n = t / g.ho;
-        const int iy = oy * S + ky - 1, ix = ox * S + kx - 1;
-        if (iy >= 0 && iy < g.he && ix >= 0 && ix < g.we) {
-          const int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
-          v = x[((n * g.hi + sy) * g.wi + sx) * CI + c];
-        }
-      }
-      sx[c][p] = v;
-    }
+  if (nsteps > 0) load(0);
+  for (int st = 0; st < nsteps; ++st) {
+    store();
     __syncthreads();
-    if (tap == 0 && tid < CO) {
+    if (st + 1 < nsteps) load(st + 1);  // in flight during this step's MFMAs
+    if (tid < CO) {
+#pragma unroll 8
       for (int p = 0; p < 32; ++p) bsum += bf2f(sdy[tid][p]);
     }
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int tile = wv + 4 * t;
-      if (tile < NT) {
-        const int tco = tile / TCI, tci = tile % TCI;
+      const int tile = wv + NW * t;
+      if (tile < NTILE) {
+        const int tap = tile / (TCO * TCI), rem = tile % (TCO * TCI);
+        const int tco = rem / TCI, tci = rem % TCI;
         const bf16x8 a = ld8(&sdy[tco * 16 + r16][kg * 8]);
-        const bf16x8 b = ld8(&sx[tci * 16 + r16][kg * 8]);
+        const bf16x8 b = ld8(&sx[tap][tci * 16 + r16][kg * 8]);
         acc[t] = mfma(a, b, acc[t]);
       }
     }
@@ -947,9 +1075,10 @@ __global__ void __launch_bounds__(256) k_conv_dw(const void* __restrict__ dy, co
   }
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
-    const int tile = wv + 4 * t;
-    if (tile >= NT) continue;
-    const int tco = tile / TCI, tci = tile % TCI;
+    const int tile = wv + NW * t;
+    if (tile >= NTILE) continue;
+    const int tap = 3 * ky0 + tile / (TCO * TCI), rem = tile % (TCO * TCI);
+    const int tco = rem / TCI, tci = rem % TCI;
     const int ci = tci * 16 + r16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -957,7 +1086,7 @@ __global__ void __launch_bounds__(256) k_conv_dw(const void* __restrict__ dy, co
       if (co < CO && ci < CI) part[((chunk * 9 + tap) * CO + co) * CI + ci] = acc[t][i];
     }
   }
-  if (tap == 0 && tid < CO) partb[chunk * CO + tid] = bsum;
+  if (ky0 == 0 && tid < CO) partb[chunk * CO + tid] = bsum;
 }
 
 // Sum the chunk partials in chunk order into the gradient vector (master layout).
@@ -1373,8 +1502,6 @@ NetDims net_dims(int32_t W, int32_t H) {
   return d;
 }
 
-constexpr int64_t kDwChunk = 2048;  // pixels per weight-gradient workgroup
-
 struct NetLayout {
   size_t bytes = 0;
   size_t off_x = 0, off_act[kLayers - 1] = {}, off_half = 0, off_ghalf = 0, off_dxe = 0, off_g[2] = {}, off_part = 0,
@@ -1402,8 +1529,7 @@ NetLayout net_layout(int32_t W, int32_t H, int64_t n, bool training) {
       gmax = std::max(gmax, (size_t)n * d.hl[l] * d.wl[l] * kNet[l].ci * 2);
     }
     for (int l = 0; l < kLayers; ++l) {
-      const int64_t M = n * (int64_t)d.hl[l + 1] * d.wl[l + 1];
-      const int64_t chunks = (M + kDwChunk - 1) / kDwChunk;
+      const int64_t chunks = dw_chunks(n * (int64_t)d.hl[l + 1]);
       part = std::max(part, (size_t)chunks * 9 * kNet[l].co * kNet[l].ci * 4);
       partb = std::max(partb, (size_t)chunks * kNet[l].co * 4);
     }
@@ -1567,12 +1693,15 @@ scn_status launch_dx(const void* dy, const uint8_t* blob, float* dxe, const CGeo
 template <int L>
 scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float* grads, const CGeom& g,
                      hipStream_t s) {
-  const int64_t M = (int64_t)g.n * g.ho * g.wo;
-  const int64_t chunks = (M + kDwChunk - 1) / kDwChunk;
+  const int64_t rows = (int64_t)g.n * g.ho;
+  const int64_t rpc = dw_rows_per_chunk(rows), chunks = dw_chunks(rows);
+  if (rows * g.wo > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
   {
+    // conv3 and conv4 (64 x 96 channel pairs): one tap row per workgroup
+    constexpr int TR = (kNet[L].ci * kNet[L].co >= 64 * 96) ? 1 : 3;
     KernelTimer timer("conv_dw", s);
-    hipLaunchKernelGGL((k_conv_dw<L>), dim3((unsigned)(chunks * 9)), dim3(256), 0, s, dy, x, b.part, b.partb, g,
-                       (int32_t)kDwChunk);
+    hipLaunchKernelGGL((k_conv_dw<L, 4, TR>), dim3((unsigned)(chunks * (3 / TR))), dim3(256), 0, s, dy, x, b.part,
+                       b.partb, g, (int32_t)rpc);
   }
   SCN_LAUNCHED("conv weight-gradient launch");
   const int64_t n = (int64_t)kNet[L].co * kNet[L].ci * 9 + kNet[L].co;
@@ -1582,19 +1711,24 @@ scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float
   return SCN_OK;
 }
 
+// Fused conv1 + conv2: output tile, waves per workgroup, workgroups per CU.
+constexpr int kConv12TOH = 4, kConv12TOW = 64, kConv12NW = 8, kConv12PerCu = 1;
+
 scn_status launch_conv12(const FrameDesc* frames, const PairDesc* pairs, const uint8_t* blob, bf16_t* y,
                           const NetDims& d, int64_t n, hipStream_t s) {
-  constexpr int TOH = FwdTile<1>::TOH, TOW = FwdTile<1>::TOW, NW = FwdTile<1>::NWAVE;
-  constexpr bool BL = FwdTile<1>::BLDS;
+  constexpr int TOH = kConv12TOH, TOW = kConv12TOW, NW = kConv12NW;
   const CGeom g1 = layer_geom(d, 0, n), g2 = layer_geom(d, 1, n);
   const int32_t tx = (g2.wo + TOW - 1) / TOW, ty = (g2.ho + TOH - 1) / TOH;
-  const int64_t grid = (int64_t)tx * ty * n;
-  if (grid > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+  const int64_t tiles = (int64_t)tx * ty * n;
+  if (tiles > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+  // one workgroup per resident slot
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * kConv12PerCu);
   KernelTimer timer("conv_fwd", s);
   KernelTimer timer_l("conv_fwd12", s);
-  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW, BL>), dim3((unsigned)grid), dim3(64 * NW), 0, s, frames, pairs, blob, y, g1,
-                     g2, tx,
-                     tx * ty);
+  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW>), dim3((unsigned)grid), dim3(64 * NW), 0, s, frames, pairs, blob, y, g1,
+                     g2, tx, tx * ty, (int32_t)tiles);
   SCN_LAUNCHED("fused conv1 + conv2 launch");
   return SCN_OK;
 }
@@ -1818,6 +1952,23 @@ scn_status scn_surrogate_grads(const scn_job* jobs, int32_t n_jobs, const void* 
   hipLaunchKernelGGL(sg::k_sum_loss, dim3(1), dim3(256), 0, s, b.loss_part, blocks, scale, loss);
   SCN_LAUNCHED("loss reduce launch");
   return sg::net_backward(d, n, blob, b, grads, s);
+}
+
+scn_status scn_surrogate_train_step(const scn_job* jobs, int32_t n_jobs, float* const* targets, float* master,
+                                    float* m, float* v, float* grads, void* net, int32_t step, float lr, float beta1,
+                                    float beta2, float eps, float* loss, void* ws, size_t ws_bytes,
+                                    scn_stream_t stream) {
+  clear_error();
+  // the Adam part's arguments first: the gradient part enqueues as soon as
+  // its own arguments check out
+  if (!master || !m || !v || !grads || !net) { set_error("NULL argument"); return SCN_EINVAL; }
+  if (step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
+    set_error("bad Adam hyper-parameters");
+    return SCN_EINVAL;
+  }
+  scn_status st = scn_surrogate_grads(jobs, n_jobs, net, targets, grads, loss, ws, ws_bytes, stream);
+  if (st != SCN_OK) return st;
+  return scn_adam_step(master, m, v, grads, step, lr, beta1, beta2, eps, net, stream);
 }
 
 scn_status scn_surrogate_infer(const scn_job* jobs, int32_t n_jobs, const void* net, float* const* flow, void* ws,

@@ -102,6 +102,10 @@ def train(data: PairSet, epochs: int = 15, batch: int = 32, seed: int = 1, lr0: 
     steps_per_epoch = data.n // batch
     total = epochs * steps_per_epoch
     tgt = torch.empty((batch, 2, data.H, data.W), dtype=torch.float32, device=dev)
+    grads = torch.empty(scn.net_params(), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_SURROGATE_GRADS, [data.job(range(batch))]), dtype=torch.uint8,
+                     device=dev)
     step = 0
     hist = []
     t0 = time.time()
@@ -110,9 +114,9 @@ def train(data: PairSet, epochs: int = 15, batch: int = 32, seed: int = 1, lr0: 
         for b in range(steps_per_epoch):
             idx = sorted(perm[b * batch:(b + 1) * batch].tolist())
             torch.index_select(data.labels, 0, torch.tensor(idx, device=dev), out=tgt)
-            grads, loss = scn.surrogate_grads([data.job(idx)], net, [tgt])
             step += 1
-            scn.adam_step(master, m, v, grads, step, cosine_lr(step, total, lr0, lr1), net)
+            grads, loss = scn.surrogate_train_step([data.job(idx)], [tgt], master, m, v, net, step,
+                                                   cosine_lr(step, total, lr0, lr1), grads=grads, loss=loss, ws=ws)
             if step % log_every == 0 or step == total:
                 lv = float(loss.item())
                 hist.append((step, lv))

@@ -183,6 +183,37 @@ def test_adam_step_parity():
     assert torch.equal(net, scn.net_pack(master))
 
 
+def test_train_step_is_grads_then_adam():
+    """scn_surrogate_train_step equals scn_surrogate_grads followed by
+    scn_adam_step bit for bit (master weights, moments, blob, gradients and
+    loss), over three steps with a changing learning rate; invalid Adam
+    arguments are refused before anything is enqueued."""
+    need_gpu()
+    W, H = 64, 48
+    tab, job = _pairs_table(W, H, 5, 17)
+    (target,) = scn.flow([job], scn.flow_params(levels=3))
+    master0, _ = _master(_params(5))
+    a = [master0.clone(), torch.zeros_like(master0), torch.zeros_like(master0)]
+    b = [master0.clone(), torch.zeros_like(master0), torch.zeros_like(master0)]
+    net_a, net_b = scn.net_pack(a[0]), scn.net_pack(b[0])
+    for t, lr in ((1, 1e-3), (2, 5e-4), (3, 2e-4)):
+        ga, la = scn.surrogate_grads([job], net_a, [target])
+        scn.adam_step(a[0], a[1], a[2], ga, t, lr, net_a)
+        gb, lb = scn.surrogate_train_step([job], [target], b[0], b[1], b[2], net_b, t, lr)
+        torch.cuda.synchronize()
+        assert torch.equal(ga, gb) and torch.equal(la, lb)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        assert torch.equal(net_a, net_b)
+    before = b[0].clone()
+    with pytest.raises(scn.ScnError):
+        scn.surrogate_train_step([job], [target], b[0], b[1], b[2], net_b, 0, 1e-3)
+    with pytest.raises(scn.ScnError):
+        scn.surrogate_train_step([job], [target], b[0], b[1], b[2], net_b, 4, 1e-3, beta1=1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(before, b[0])
+
+
 def test_training_steps_reduce_loss():
     need_gpu()
     W, H = 64, 48
