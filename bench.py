@@ -30,8 +30,11 @@ W, H, N_ROWS = 1920, 1080, 2400
 LEVELS, ALPHA, ITERS = 4, 10.0, 50
 FB_ITERS = 3  # Farnebäck displacement iterations per level
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
+# FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.
+# The published 157.3 TFLOP/s counts packed FP32 (two lanes of work per
+# instruction), which these kernels do not emit; both are reported.
 FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+FP32_PUBLISHED_TFLOPS = 157.3
 # the oracle's Jacobi update: two neighbour averages (9 each) + the update (9)
 FLOP_PER_PX_SWEEP = 27
 BF16_PEAK_TFLOPS = 2500.0
@@ -60,7 +63,7 @@ def _oracle_pair(args):
 
 def cpu_baseline(tab, pairs, max_pairs=None):
     cores = len(os.sched_getaffinity(0))
-    n = min(len(pairs), max_pairs or cores)
+    n = min(len(pairs), max_pairs or len(pairs))
     sample = pairs[:: max(1, len(pairs) // n)][:n]
     frames = [(tab[a].cpu().numpy().reshape(H * 3 // 2, W), tab[b].cpu().numpy().reshape(H * 3 // 2, W))
               for a, b in sample]
@@ -71,8 +74,8 @@ def cpu_baseline(tab, pairs, max_pairs=None):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "frames/s", "cores": min(cores, n), "kind": "oracle",
             "cpu": _cpu_model(),
-            "sample": "%d of the workload's 122 pairs (HIST of the first frame + FP64 Horn-Schunck L=4, "
-                      "50 iters), one pair per process, %.1f s wall" % (done, dt)}
+            "sample": "%d of the workload's %d pairs (HIST of the first frame + FP64 Horn-Schunck L=4, "
+                      "50 iters), one pair per process, %.1f s wall" % (done, len(pairs), dt)}
 
 
 def _jacobi_timing(scn):
@@ -210,6 +213,59 @@ def farneback_leg(scn, torch, dev, jobs, hists, ws_hist, stream, m_total, p_tota
                         "achieved_GBps": poly_bytes / (poly_ms * 1e-3) / 1e9,
                         "frac": poly_bytes / (poly_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "launches": poly_n},
             "note": "HIST + Farnebäck flow over the same 124 frames / 122 pairs as the headline step"}
+
+
+def training_leg(scn, torch, dev, steps=20, batch=32, n_pairs=128):
+    """Surrogate training throughput: scn_surrogate_train_step (forward,
+    Charbonnier loss, dX, dW, Adam) on batches of 32 seeded 512 x 384 pairs
+    labelled by the plain solver, the trainer's configuration.  MFMA work per
+    sample = the forward convolutions (half resolution) + the same again for
+    the weight gradients + the input gradients of conv2..conv6."""
+    from paper_1805_07339_amd import train as T
+    data = T.PairSet(n_pairs, 512, 384, seed=4_000_000, device=dev)
+    data.label_all()
+    master = T.he_init(1).to(dev)
+    m, v = torch.zeros_like(master), torch.zeros_like(master)
+    net = scn.net_pack(master)
+    tgt = torch.empty((batch, 2, 384, 512), dtype=torch.float32, device=dev)
+    grads = torch.empty(scn.net_params(), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_SURROGATE_GRADS, [data.job(range(batch))]), dtype=torch.uint8,
+                     device=dev)
+    g = torch.Generator().manual_seed(1)
+    batches = []
+    for _ in range(steps + 2):
+        idx = sorted(torch.randperm(n_pairs, generator=g)[:batch].tolist())
+        batches.append((data.job(idx), torch.tensor(idx, device=dev)))
+
+    def run(k, st):
+        job, ix = batches[k]
+        torch.index_select(data.labels, 0, ix, out=tgt)
+        scn.surrogate_train_step([job], [tgt], master, m, v, net, st, 1e-3, grads=grads, loss=loss, ws=ws)
+
+    run(0, 1)
+    run(1, 2)
+    torch.cuda.synchronize()
+    scn.timing_enable(True, 1 << 16)
+    scn.timing_reset()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        run(k + 2, k + 3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {k: scn.timing_read(k)[0] / steps for k in ("conv_fwd", "conv_dx", "conv_dw")}
+    scn.timing_enable(False)
+    lf = _layer_flops(512, 384)
+    flop = 2 * sum(lf) + sum(lf[1:])  # forward + weight gradients + input gradients (none for conv1)
+    tflops = flop * batch * steps / dt / 1e12
+    dw_flop = sum(lf) * batch
+    return {"samples_per_s": batch * steps / dt, "ms_per_step": dt / steps * 1e3, "batch": batch,
+            "pair_size": "512x384", "flop_per_sample": flop, "achieved_TFLOPs": tflops,
+            "mfma_utilisation": tflops / BF16_PEAK_TFLOPS,
+            "ms_per_step_by_kernel": kern,
+            "conv_dw_TFLOPs": dw_flop / (kern["conv_dw"] * 1e-3) / 1e12 if kern["conv_dw"] > 0 else None,
+            "note": "train-step time includes the label gather, loss and Adam; the per-kernel times come from the "
+                    "library's event timers in the same steps"}
 
 
 def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_total, args):
@@ -381,12 +437,18 @@ def c3_workload(scn, torch, dev, args):
                 c()
     torch.cuda.current_stream().wait_stream(side)
     g.replay()
+    # one-byte fills of an int8 tensor before and after the timed replays
+    # mark them in a kernel trace (bench.py --gap-summary)
+    mark = torch.empty(16, dtype=torch.int8, device=dev)
+    mark.fill_(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.replay()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    mark.fill_(2)
+    torch.cuda.synchronize()
     frames = sum(scn.count_rows(j) for j in jobs.values())
     pairs = sum(scn.count_pairs(j) for j in jobs.values())
     px_sweeps = sum(scn.count_pairs(j) * _px_levels(j.table.width, j.table.height, LEVELS)
@@ -503,6 +565,98 @@ def c5_workload(scn, torch, dev, args):
             "surrogate": sur}
 
 
+def gap_summary(directory: str) -> str:
+    """Launch gaps of the timed graph replays of `--workload c3` from a
+    rocprofv3 kernel trace: the kernels between the run's two int8 fill
+    markers, their busy time (union of kernel intervals), the idle time
+    between launches and its share of the replay, and the gap distribution."""
+    import csv
+    import glob
+    ks = []
+    for f in glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            ks.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    ks.sort()
+    marks = [i for i, (_, _, n) in enumerate(ks) if "FillFunctor<signed char>" in n]
+    if len(marks) < 2:
+        return "# no replay markers in the trace"
+    win = ks[marks[-2] + 1:marks[-1]]
+    t0, t1 = win[0][0], max(e for _, e, _ in win)
+    busy, cur_s, cur_e = 0, win[0][0], win[0][1]
+    gaps = []
+    for s0, e0, _ in win[1:]:
+        if s0 > cur_e:
+            busy += cur_e - cur_s
+            gaps.append(s0 - cur_e)
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    busy += cur_e - cur_s
+    wall = t1 - t0
+    fam = {}
+    for s0, e0, n in win:
+        k = n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].split("<")[0]
+        c, t = fam.get(k, (0, 0))
+        fam[k] = (c + 1, t + e0 - s0)
+    gaps_sorted = sorted(gaps)
+    q = lambda p: gaps_sorted[min(len(gaps_sorted) - 1, int(p * len(gaps_sorted)))] if gaps_sorted else 0
+    out = ["launches %d" % len(win), "replay_wall_ms %.3f" % (wall / 1e6), "busy_ms %.3f" % (busy / 1e6),
+           "idle_between_launches_ms %.3f" % ((wall - busy) / 1e6),
+           "idle_fraction %.4f" % ((wall - busy) / wall),
+           "gaps %d  median_us %.2f  p90_us %.2f  max_us %.2f" % (len(gaps), q(0.5) / 1e3, q(0.9) / 1e3,
+                                                                 (gaps_sorted[-1] if gaps else 0) / 1e3),
+           "# per kernel: launches, summed duration (ms)"]
+    for k in sorted(fam):
+        out.append("kernel %-40s %6d %10.3f" % (k, fam[k][0], fam[k][1] / 1e6))
+    return "\n".join(out)
+
+
+def sq_summary(directory: str) -> str:
+    """Per-kernel SQ counters of one or more rocprofv3 --pmc runs (values
+    summed over each kernel's dispatches) with derived ratios: instructions
+    per wave, the share of a wave's cycles in which it issued VALU / LDS /
+    memory instructions, LDS issue stalls per LDS instruction and LDS bank
+    conflicts per LDS instruction."""
+    import csv
+    import glob
+    agg = {}
+    for f in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r.get("Kernel_Name", "")
+            if "scn::" not in name:
+                continue
+            k = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0].replace(" ", "")
+            c = r.get("Counter_Name", "")
+            agg.setdefault(k, {})
+            agg[k][c] = agg[k].get(c, 0.0) + float(r.get("Counter_Value", 0) or 0)
+    names = sorted({c for v in agg.values() for c in v})
+    out = ["# counters (summed over the dispatches of each kernel): " + " ".join(names),
+           "# derived: per-wave instruction counts; active_* = SQ_ACTIVE_INST_* / SQ_WAVE_CYCLES (share of wave "
+           "cycles issuing that class); lds_wait_per_lds = SQ_WAIT_INST_LDS / SQ_INSTS_LDS; bank_conflict_per_lds = "
+           "SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS"]
+    for k in sorted(agg):
+        v = agg[k]
+        waves = v.get("SQ_WAVES", 0.0)
+        wc = v.get("SQ_WAVE_CYCLES", 0.0)
+        d = []
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU",
+                  "SQ_INSTS_VALU_MFMA_MOPS_BF16"):
+            if c in v and waves:
+                d.append("%s/wave %.1f" % (c[9:].lower(), v[c] / waves))
+        for c in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM", "SQ_WAIT_ANY",
+                  "SQ_ACTIVE_INST_ANY"):
+            if c in v and wc:
+                d.append("%s %.3f" % (c.replace("SQ_", "").lower(), v[c] / wc))
+        if "SQ_WAIT_INST_LDS" in v and v.get("SQ_INSTS_LDS"):
+            d.append("lds_wait_per_lds %.2f" % (v["SQ_WAIT_INST_LDS"] / v["SQ_INSTS_LDS"]))
+        if "SQ_LDS_BANK_CONFLICT" in v and v.get("SQ_ACTIVE_INST_LDS"):
+            d.append("bank_conflict_per_lds %.3f" % (v["SQ_LDS_BANK_CONFLICT"] / v["SQ_ACTIVE_INST_LDS"]))
+        out.append("%s" % k)
+        out.append("    raw: " + "  ".join("%s=%.4g" % (c, v[c]) for c in sorted(v)))
+        out.append("    derived: " + "; ".join(d))
+    return "\n".join(out)
+
+
 def summarize_rocprof(directory: str, bench_json: str = None) -> str:
     """Short text summary of rocprofv3 CSV output (kernel stats of this library's
     kernels, and per-kernel sums of any collected counters).  With the bench
@@ -512,15 +666,24 @@ def summarize_rocprof(directory: str, bench_json: str = None) -> str:
     import glob
     out = []
     if bench_json:
+        # the Jacobi launches of the timed steps: between the run's two int8
+        # fill markers (bench.py's own average comes from a second pass of the
+        # same steps with its event timers)
         info = json.loads(open(bench_json).read().strip().splitlines()[-1])
-        n = int(info["roofline"]["launches"])
         for f in sorted(glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)):
-            d = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-                 for r in csv.DictReader(open(f)) if "k_hs_jacobi" in r["Kernel_Name"]]
-            d = [x for _, x in sorted(d)][-n:]
-            out.append("# timed region of the profiled run: %d Jacobi launches, average %.1f ns "
-                       "(bench.py's own HIP-event average in the same run: %.1f ns)"
-                       % (len(d), sum(d) / max(len(d), 1), info["roofline"]["avg_launch_ms"] * 1e6))
+            ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                        for r in csv.DictReader(open(f)))
+            marks = [i for i, k in enumerate(ks) if "FillFunctor<signed char>" in k[2]]
+            if len(marks) < 2 or marks[1] == marks[0] + 1:
+                continue
+            win = ks[marks[0] + 1:marks[1]]
+            d = [e - s0 for s0, e, n in win if "k_hs_jacobi" in n]
+            wall = max(e for _, e, _ in win) - win[0][0]
+            out.append("# timed region of the profiled run (%d steps): %d Jacobi launches, average %.1f ns "
+                       "(bench.py's own HIP-event average in the same run: %.1f ns); wall %.3f ms per step "
+                       "(bench.py: %.3f)" % (info["steps"], len(d), sum(d) / max(len(d), 1),
+                                            info["roofline"]["avg_launch_ms"] * 1e6, wall / 1e6 / info["steps"],
+                                            info["ms_per_step"]))
     def short(n):
         n = n.replace("(anonymous namespace)::", "").replace("void ", "")
         return n.split("(")[0]
@@ -606,6 +769,19 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         res[ctr] = (factor, copy, sum(jac) * 1024.0 * factor, len(jac))
     fb, wb = res["FETCH_SIZE"][2], res["WRITE_SIZE"][2]
     alg = info["roofline"]["px_sweeps"] * 28.0
+    steps = int(info["steps"])
+    comp = float(info["roofline"].get("compulsory_bytes_per_launch") or 0.0) * n_launch
+    # every library kernel: mean HBM bytes per dispatch over the whole run
+    per_kernel = {}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        factor = res[ctr][0]
+        for _, n, v in rows(d):
+            if "scn::" not in n:
+                continue
+            k = n.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            ent = per_kernel.setdefault(k, {})
+            tot, cnt = ent.get(ctr, (0.0, 0))
+            ent[ctr] = (tot + v * 1024.0 * factor, cnt + 1)
     # the large HIST and conversion launches (the largest dispatch of each kernel)
     big = {}
     for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
@@ -620,7 +796,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         "# colour source sha256(color.hip) = %s" % _source_hash(("color.hip",)),
         "# commands (from the repository root, cd /tmp && export TMPDIR=/tmp first):",
         "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o run -- python3 bench.py --steps 1 --warmup 1 "
-        "--no-cpu-baseline --no-surrogate --no-extras --calib-copy",
+        "--no-cpu-baseline --no-surrogate --no-extras --no-farneback --calib-copy",
         "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o run -- python3 bench.py (same arguments)",
         "#   python3 bench.py --traffic-summary <F> <W> <bench json of the FETCH run>",
         "# copy calibration (1 GiB device copy): FETCH_SIZE %.1f KiB -> factor %.4f; WRITE_SIZE %.1f KiB -> factor %.4f"
@@ -631,13 +807,23 @@ def traffic_summary(fetch_dir: str, write_dir: str, bench_json: str) -> str:
         "traffic_bytes_per_launch %.0f" % ((fb + wb) / n_launch),
         "streaming_algorithmic_bytes_per_step %.0f  (28 B per pixel-sweep)" % alg,
         "traffic_over_streaming_algorithmic %.4f" % ((fb + wb) / alg),
+        "compulsory_bytes_per_step %.0f  (28 B per pixel and pass: u, v, a, b, c read and u, v written once)"
+        % comp,
+        "traffic_over_compulsory %.4f" % ((fb + wb) / comp if comp else float("nan")),
         "hist_bytes_per_launch %.0f  (%d frames; algorithmic %.0f)" % (
             big[("k_hist16", "FETCH_SIZE")] + big[("k_hist16", "WRITE_SIZE")], info["hist"]["frames_per_launch"],
             info["hist"]["algorithmic_bytes_per_frame"] * info["hist"]["frames_per_launch"]),
         "convert_bytes_per_launch %.0f  (%d frames; algorithmic %.0f)" % (
             big[("k_nv12_rgb24", "FETCH_SIZE")] + big[("k_nv12_rgb24", "WRITE_SIZE")],
             info["convert_rgb24"]["frames_per_launch"], 4.5 * W * H * info["convert_rgb24"]["frames_per_launch"]),
+        "# every library kernel of the run: mean HBM bytes per dispatch (copy-calibrated)",
+        "# %-58s %10s %16s %16s" % ("kernel", "dispatches", "fetch_B", "write_B"),
     ]
+    for k in sorted(per_kernel):
+        f_tot, f_n = per_kernel[k].get("FETCH_SIZE", (0.0, 0))
+        w_tot, w_n = per_kernel[k].get("WRITE_SIZE", (0.0, 0))
+        lines.append("kernel %-58s %10d %16.0f %16.0f" % (k.replace(" ", ""), max(f_n, w_n), f_tot / max(f_n, 1),
+                                                          w_tot / max(w_n, 1)))
     return "\n".join(lines)
 
 
@@ -653,7 +839,7 @@ def read_counter_summary():
             src = line.split("=")[-1].strip()
         elif line.startswith("# colour source sha256"):
             csrc = line.split("=")[-1].strip()
-        elif not line.startswith("#") and line.strip():
+        elif not line.startswith("#") and line.strip() and not line.startswith("kernel "):
             k, v = line.split()[:2]
             kv[k] = float(v)
     if csrc != _source_hash(("color.hip",)):  # HIST / conversion counters describe older colour kernels
@@ -677,6 +863,12 @@ def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-rocprof":
         print(summarize_rocprof(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else None))
         return
+    if len(sys.argv) > 2 and sys.argv[1] == "--sq-summary":
+        print(sq_summary(sys.argv[2]))
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--gap-summary":
+        print(gap_summary(sys.argv[2]))
+        return
     if len(sys.argv) > 4 and sys.argv[1] == "--traffic-summary":
         print(traffic_summary(sys.argv[2], sys.argv[3], sys.argv[4]))
         return
@@ -685,12 +877,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=0, help="pairs in the CPU-baseline sample (0: one per core)")
+    ap.add_argument("--cpu-pairs", type=int, default=0, help="pairs in the CPU-baseline sample (0: every pair of the step)")
     ap.add_argument("--sweeps-per-pass", type=int, default=0)
     ap.add_argument("--weights", default=None, help="surrogate checkpoint (default: the packaged one)")
     ap.add_argument("--tau", type=float, default=None, help="gate threshold (default: the calibrated one)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-farneback", action="store_true", help="skip the Farnebäck leg")
+    ap.add_argument("--no-training", action="store_true", help="skip the surrogate training-throughput leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the stencil-before-sampling and warm-start legs (profiled runs: their Jacobi "
                          "launches would follow the timed step's)")
@@ -753,6 +946,10 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # one-byte fills of an int8 tensor before and after the timed steps mark
+    # them in a kernel trace (bench.py --summarize-rocprof)
+    mark = torch.empty(16, dtype=torch.int8, device=dev)
+    mark.fill_(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -760,6 +957,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = t1 - t0
+    mark.fill_(2)
+    torch.cuda.synchronize()
     # per-kernel times: the same steps again, with the library's HIP-event
     # timers around each launch (kept out of the timed pass above)
     scn.timing_enable(True, 1 << 20)
@@ -784,6 +983,11 @@ def main():
     jac_n = sum(kern["hs_jacobi_l%d" % l][1] for l in range(LEVELS))
     jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps / (jac_ms * 1e-3) / 1e12
     jac_stream_gbs = 28.0 * px_sweeps / (jac_ms * 1e-3) / 1e9
+    # compulsory HBM bytes of the Jacobi launches: one launch runs one pass
+    # (up to K sweeps) over a level and must read u, v, a, b, c and write u, v
+    # once per pixel (28 B), whatever K is
+    jac_compulsory = sum(28.0 * w * h * p_total * kern["hs_jacobi_l%d" % l][1] / args.steps
+                         for l, (w, h) in enumerate(lv)) * args.steps
     hist_ms_step, hist_n_step = kern["hist16"]
 
     # --- HIST and conversion bandwidth on a large batch (beyond the 256 MB MALL)
@@ -824,6 +1028,7 @@ def main():
     farneback = (None if args.no_farneback else
                  farneback_leg(scn, torch, dev, jobs, hists, ws_hist, stream, m_total, p_total, args.steps,
                                args.warmup))
+    training = None if (args.no_training or args.no_surrogate) else training_leg(scn, torch, dev)
     surrogate = (None if args.no_surrogate else
                  surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, flows, stream, m_total, args))
     if args.calib_copy:
@@ -851,7 +1056,14 @@ def main():
                                "%d iters" % (LEVELS, ALPHA, ITERS),
                    "frames_per_step": m_total, "pairs_per_step": p_total, "width": W, "height": H},
         "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS,
+                     "peak_note": "FP32 VALU without packed FP32 (256 CUs x 64 lanes x 2 FLOP x 2.4 GHz); "
+                                  "frac_of_published is against the datasheet's 157.3 TFLOP/s, which counts "
+                                  "packed FP32",
+                     "peak_published": FP32_PUBLISHED_TFLOPS, "frac_of_published": jac_tflops / FP32_PUBLISHED_TFLOPS,
+                     "traffic": traffic,
+                     "compulsory_bytes_per_launch": jac_compulsory / max(jac_n, 1),
+                     "traffic_over_compulsory": (traffic / (jac_compulsory / max(jac_n, 1)) if traffic else None),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
                      # measured HBM rate of the Jacobi launches: counter bytes per launch / HIP-event time
@@ -879,6 +1091,7 @@ def main():
                           "counter_GBps": (ctr_kv["convert_bytes_per_launch"] / (conv_ms / max(conv_n, 1) * 1e-3) / 1e9
                                            if "convert_bytes_per_launch" in ctr_kv else None)},
         "farneback": farneback,
+        "surrogate_training": training,
         "surrogate": surrogate,
         "surrogate_over_plain_frames_per_s": (surrogate["value"] / (m_total * args.steps / dt)
                                               if surrogate and "value" in surrogate else None),

@@ -909,7 +909,8 @@ struct JacobiVariant {
 };
 constexpr JacobiVariant kVariants[] = {{1, 4, 0, 0},     {8, 16, 0, 0},    {16, 8, 0, 0},    {8, 8, 0, 0},
                                        {4, 16, 0, 0},    {0, 6, 256, 3},   {0, 8, 256, 3},   {0, 10, 256, 3},
-                                       {0, 10, 1024, 3}, {0, 10, 256, 6},  {0, 10, 1024, 6}};
+                                       {0, 10, 1024, 3}, {0, 10, 256, 6},  {0, 10, 1024, 6}, {0, 12, 256, 3},
+                                       {0, 12, 1024, 3}, {0, 12, 256, 6},  {0, 12, 1024, 6}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultStreaming = 9;  // K <= 10, 6 rows in flight: the masked (fallback) default
 
@@ -974,11 +975,14 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     const dim3 gd((unsigned)grid), bd(256);
     if (K == 10 && v.prefetch == 6) {
       hipLaunchKernelGGL((k_hs_jacobi_st<10, 6>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+    } else if (K == 12 && v.prefetch == 6) {
+      hipLaunchKernelGGL((k_hs_jacobi_st<12, 6>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
     } else {
       switch (K) {
 #define SCN_ST(k) \
   case k: hipLaunchKernelGGL((k_hs_jacobi_st<k, 3>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
         SCN_ST(1) SCN_ST(2) SCN_ST(3) SCN_ST(4) SCN_ST(5) SCN_ST(6) SCN_ST(7) SCN_ST(8) SCN_ST(9) SCN_ST(10)
+        SCN_ST(11) SCN_ST(12)
 #undef SCN_ST
         default: set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL;
       }
