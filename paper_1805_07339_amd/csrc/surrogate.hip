@@ -1089,19 +1089,20 @@ __global__ void __launch_bounds__(64 * NW) k_conv_dw(const void* __restrict__ dy
   if (ky0 == 0 && tid < CO) partb[chunk * CO + tid] = bsum;
 }
 
-// Sum the chunk partials in chunk order into the gradient vector (master layout).
+// Sum the chunk partials in chunk order into the gradient vector (master
+// layout [co][ci][ky][kx]).  Thread i takes partial index i ([tap][co][ci]
+// order), so that a wave reads consecutive floats of every chunk.
 __global__ void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ partb, float* __restrict__ grads,
                             int64_t chunks, int32_t ci, int32_t co, int32_t w_off, int32_t b_off) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nw = (int64_t)co * ci * 9;
   if (i < nw) {
-    // master layout [co][ci][ky][kx]
-    const int tap = (int)(i % 9);
-    const int64_t t = i / 9;
-    const int c_in = (int)(t % ci), c_out = (int)(t / ci);
+    const int c_in = (int)(i % ci);
+    const int64_t t = i / ci;
+    const int c_out = (int)(t % co), tap = (int)(t / co);
     float s = 0.f;
-    for (int64_t k = 0; k < chunks; ++k) s += part[((k * 9 + tap) * co + c_out) * ci + c_in];
-    grads[w_off + i] = s;
+    for (int64_t k = 0; k < chunks; ++k) s += part[k * nw + i];
+    grads[w_off + ((int64_t)c_out * ci + c_in) * 9 + tap] = s;
   } else if (i < nw + co) {
     const int c_out = (int)(i - nw);
     float s = 0.f;
