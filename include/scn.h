@@ -133,13 +133,15 @@ typedef struct {
  * `sweeps_per_pass` and `tile_variant` select the Jacobi schedule: 0 and 0
  * let the library's autotuner choose (tuned once per level shape, see
  * SCN_TUNE_CACHE / SCN_TUNE in the implementation notes); sweeps_per_pass = 1
- * with tile_variant = 0 runs one sweep per launch; otherwise sweeps_per_pass
- * sweeps (1..63) run per launch on register tiles of variant 1..4 (128 x 128,
- * 128 x 128, 128 x 64, 128 x 64 pixels), or on 128-column strips streamed
- * row by row with variants 5..10 (at most 6, 8, 10, 10, 10, 10 sweeps per
- * launch; variants 8 and 10 stream bands of up to 1024 rows instead of 256;
- * variants 9 and 10 keep six input rows in flight instead of three).  Every
- * schedule gives bitwise identical results.
+ * with tile_variant = 0 runs one sweep per launch; otherwise the `iters`
+ * sweeps of a level run in ceil(iters / k) launches of nearly equal sweep
+ * counts, k = sweeps_per_pass (1..63), on register tiles of variant 1..4
+ * (128 x 128, 128 x 128, 128 x 64, 128 x 64 pixels), or on 128-column strips
+ * streamed row by row with variants 5..18, where k is also capped at the
+ * variant's largest sweep count (6, 8, 10, 10, 10, 10, 12, 12, 12, 12, 13,
+ * 13, 17, 17; variants 8, 10, 12, 14, 16 and 18 stream bands of up to 1024
+ * rows instead of 256; variants 9, 10, 13 and 14 keep six input rows in
+ * flight instead of three).  Every schedule gives bitwise identical results.
  * Temporal warm start (scn_flow only; a bounded-state operation with warmup
  * W = 1, Sec. 3.2): with `warm_packet` G >= 2 the pairs of each slice are cut
  * into work packets of G consecutive pairs from the slice's first pair.  The

@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(64 * NW) k_hs_jacobi_tb(ChunkPtrs c, LevelGeom
 // and advances every row in flight by one sweep, so that after the step
 // sweep s holds row i - s.  Sweep s keeps its last three rows in VGPRs (the
 // step loop is unrolled by 3 so their slots are static); the coefficients of
-// the K + 1 rows in flight sit in a per-wave LDS ring.  There is no vertical
+// the last K input rows sit in a per-wave LDS ring.  There is no vertical
 // halo tile and no barrier: waves are independent, which lets the loads of
 // one wave overlap the arithmetic of another.  Rows above and below the
 // image are mirrored, which reproduces clamp-to-edge bitwise (same argument
@@ -659,7 +659,7 @@ __device__ __forceinline__ gfloat& at_off(float* base, uint32_t byte_off) {
 template <int K>
 struct StStep {
   float4 (&win)[K][3];
-  float2 (&ring)[K + 1][3][64];
+  float2 (&ring)[K][3][64];
   int lane;
   int32_t y0, y1, w;
   float* du;
@@ -668,17 +668,32 @@ struct StStep {
   bool in0, in1;
   bool vec;           // wave-uniform: 8-byte accesses (see the kernel)
 
+  struct Coef {
+    float2 a, b, c;
+  };
+  __device__ __forceinline__ Coef ring_row(int32_t row) const {
+    const int rr = ((row % K) + K) % K;
+    return Coef{ring[rr][0][lane], ring[rr][1][lane], ring[rr][2][lane]};
+  }
+
+  // Sweep S advances row ii - S with the coefficients `co` of that row,
+  // which were read from the ring one sweep earlier (the reads of sweep
+  // S + 1's row are issued ahead of sweep S's arithmetic); `last` holds row
+  // ii - K for sweep K, read at the start of the step.
   template <int U, int S>
-  __device__ __forceinline__ void sweep(int32_t ii) {
+  __device__ __forceinline__ void sweep(int32_t ii, const Coef& co, const Coef& last) {
     if constexpr (S <= K) {
-      constexpr int RING = K + 1;
+      Coef nx;
+      if constexpr (S + 1 < K) {
+        nx = ring_row(ii - S - 1);
+        __builtin_amdgcn_sched_barrier(0);
+      } else if constexpr (S + 1 == K) {
+        nx = last;
+      }
       const float4 A = win[S - 1][(U - S + 2 + 3 * K) % 3];
       const float4 B = win[S - 1][(U - S + 3 * K) % 3];
       const float4 C = win[S - 1][(U - S + 1 + 3 * K) % 3];
-      const int rr = (((ii - S) % RING) + RING) % RING;
-      const float2 ca = ring[rr][0][lane];
-      const float2 cb = ring[rr][1][lane];
-      const float2 cc = ring[rr][2][lane];
+      const float2 ca = co.a, cb = co.b, cc = co.c;
       const float qu0 = A.x + C.x, qu1 = A.y + C.y, qv0 = A.z + C.z, qv1 = A.w + C.w;
       const float cu0 = fmaf(B.x, 2.f, qu0), cu1 = fmaf(B.y, 2.f, qu1);
       const float cv0 = fmaf(B.z, 2.f, qv0), cv1 = fmaf(B.w, 2.f, qv1);
@@ -720,25 +735,29 @@ struct StStep {
         }
         return;
       }
-      sweep<U, S + 1>(ii);
+      sweep<U, S + 1>(ii, nx, last);
     }
   }
 
   // Input row ii sits in prefetch slot U of P (P a multiple of 3, so that
   // ii mod 3 = U mod 3 selects the window slot); once it has entered the
   // window and the ring, the slot is refilled with row ii + P (P rows of
-  // loads in flight per wave).
+  // loads in flight per wave).  The ring has K slots: row ii takes the slot
+  // of row ii - K, whose coefficients (needed by sweep K in this step) are
+  // read first; the LDS operations of a wave execute in order.
   template <int U, int P, typename F>
   __device__ __forceinline__ void step(int32_t ii, float4 (&nuv)[P], float2 (&na)[P], float2 (&nb)[P],
                                        float2 (&nc)[P], F&& load_row) {
-    constexpr int RING = K + 1, W = U % 3;
+    constexpr int W = U % 3;
     win[0][W] = nuv[U];
-    const int rs = ((ii % RING) + RING) % RING;
+    const Coef last = ring_row(ii - K);
+    const int rs = ((ii % K) + K) % K;
     ring[rs][0][lane] = na[U];
     ring[rs][1][lane] = nb[U];
     ring[rs][2][lane] = nc[U];
     load_row(ii + P, nuv[U], na[U], nb[U], nc[U]);
-    sweep<W, 1>(ii);
+    if constexpr (K == 1) sweep<W, 1>(ii, last, last);
+    else sweep<W, 1>(ii, ring_row(ii - 1), last);
   }
   // steps U .. P-1 of one loop iteration (rows i + U ..)
   template <int U, int P, typename F>
@@ -749,11 +768,10 @@ struct StStep {
   }
 };
 
-template <int K, int P>
-__global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
+template <int K, int P, int WB>
+__global__ void __launch_bounds__(64 * WB) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
                                                       int32_t strips, int32_t bands, int32_t band_h) {
-  constexpr int RING = K + 1;
-  __shared__ float2 ring[4][RING][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
+  __shared__ float2 ring[WB][K][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
   const int lane = threadIdx.x & 63;
   // wave-uniform from here on: the pair, band, strip, row counters and plane
   // pointers live in SGPRs and their arithmetic runs on the scalar unit
@@ -762,7 +780,7 @@ __global__ void __launch_bounds__(256) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, 
   // A wave takes unit (pair, band, strip) = its index; with an active-pair
   // list the units index list slots, and the grid (sized for a fraction of
   // the pairs) strides over them until the list is exhausted.
-  for (int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wv;; unit += (int64_t)gridDim.x * 4) {
+  for (int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WB + wv;; unit += (int64_t)gridDim.x * WB) {
     int64_t pr;
     if (c.act_list) {
       const int64_t slot = unit / per_pair;
@@ -910,7 +928,8 @@ struct JacobiVariant {
 constexpr JacobiVariant kVariants[] = {{1, 4, 0, 0},     {8, 16, 0, 0},    {16, 8, 0, 0},    {8, 8, 0, 0},
                                        {4, 16, 0, 0},    {0, 6, 256, 3},   {0, 8, 256, 3},   {0, 10, 256, 3},
                                        {0, 10, 1024, 3}, {0, 10, 256, 6},  {0, 10, 1024, 6}, {0, 12, 256, 3},
-                                       {0, 12, 1024, 3}, {0, 12, 256, 6},  {0, 12, 1024, 6}};
+                                       {0, 12, 1024, 3}, {0, 12, 256, 6},  {0, 12, 1024, 6}, {0, 13, 256, 3},
+                                       {0, 13, 1024, 3}, {0, 17, 256, 3},  {0, 17, 1024, 3}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr int kDefaultStreaming = 9;  // K <= 10, 6 rows in flight: the masked (fallback) default
 
@@ -970,19 +989,24 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     // with an active-pair list the grid covers n_eff pairs' units and the
     // waves stride over the list (an empty list costs one short launch)
     const int64_t units = (int64_t)strips * bands * (c.act_list ? n_eff : n_pairs);
-    const int64_t grid = (units + 3) / 4;
+    // Waves per workgroup: each wave's coefficient ring takes K x 1.5 KiB of
+    // LDS, so that 8 waves (two workgroups) fit a CU's 160 KiB up to K = 13;
+    // larger K run one wave per workgroup (6 or 7 per CU).
+    const int wb = K <= 13 ? 4 : 1;
+    const int64_t grid = (units + wb - 1) / wb;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
-    const dim3 gd((unsigned)grid), bd(256);
+    const dim3 gd((unsigned)grid), bd(64 * wb);
     if (K == 10 && v.prefetch == 6) {
-      hipLaunchKernelGGL((k_hs_jacobi_st<10, 6>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+      hipLaunchKernelGGL((k_hs_jacobi_st<10, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
     } else if (K == 12 && v.prefetch == 6) {
-      hipLaunchKernelGGL((k_hs_jacobi_st<12, 6>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+      hipLaunchKernelGGL((k_hs_jacobi_st<12, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
     } else {
       switch (K) {
-#define SCN_ST(k) \
-  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k, 3>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
-        SCN_ST(1) SCN_ST(2) SCN_ST(3) SCN_ST(4) SCN_ST(5) SCN_ST(6) SCN_ST(7) SCN_ST(8) SCN_ST(9) SCN_ST(10)
-        SCN_ST(11) SCN_ST(12)
+#define SCN_ST(k, wbk) \
+  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k, 3, wbk>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
+        SCN_ST(1, 4) SCN_ST(2, 4) SCN_ST(3, 4) SCN_ST(4, 4) SCN_ST(5, 4) SCN_ST(6, 4) SCN_ST(7, 4) SCN_ST(8, 4)
+        SCN_ST(9, 4) SCN_ST(10, 4) SCN_ST(11, 4) SCN_ST(12, 4) SCN_ST(13, 4) SCN_ST(14, 1) SCN_ST(15, 1)
+        SCN_ST(16, 1) SCN_ST(17, 1)
 #undef SCN_ST
         default: set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL;
       }
@@ -1218,8 +1242,11 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
     int32_t cur = start_dst;
     if (prm.iters > 0) {
       const JacobiChoice jc = choose_jacobi(grp, l, ch.n_pairs, prm, c, g, cur, s);
-      for (int32_t done = 0; done < prm.iters;) {
-        const int32_t ns = std::min(jc.k, prm.iters - done);
+      // ceil(iters / k) passes of nearly equal sweep counts (50 = 13+13+12+12
+      // rather than 13+13+13+11; results do not depend on the split)
+      const int32_t passes = (prm.iters + jc.k - 1) / jc.k;
+      for (int32_t done = 0, pass = 0; done < prm.iters; ++pass) {
+        const int32_t ns = prm.iters / passes + (pass < prm.iters % passes ? 1 : 0);
         const int32_t dst = (l == 0 && done + ns == prm.iters) ? 2 : 1 - cur;
         st = launch_jacobi(jc, c, g, ch.n_pairs, cur, dst, ns, s);
         if (st != SCN_OK) return st;

@@ -197,7 +197,7 @@ scn_status check_flow_params(const scn_flow_params* p, const scn_table* t) {
     set_error("sweeps_per_pass must be in [0, 63]");
     return SCN_EINVAL;
   }
-  if (p->tile_variant < 0 || p->tile_variant > 14) { set_error("tile_variant must be in [0, 14]"); return SCN_EINVAL; }
+  if (p->tile_variant < 0 || p->tile_variant > 18) { set_error("tile_variant must be in [0, 18]"); return SCN_EINVAL; }
   if (p->warm_packet < 0 || p->warm_packet > (1 << 20)) {
     set_error("warm_packet must be in [0, 2^20]");
     return SCN_EINVAL;

@@ -240,8 +240,8 @@ def test_jacobi_schedules_are_bitwise_identical(w, h, levels):
     ref = ref.clone()
     exp = _oracle_pairs(tab, [(0, 1), (1, 2)], w, h, w, levels)
     assert _maxdiff(ref.cpu().numpy(), exp) <= TOL
-    for variant in range(1, 11):
-        for k in (2, 5, 8, 13):
+    for variant in range(1, 19):
+        for k in (2, 5, 8, 13, 17):
             (f,) = scn.flow([job], scn.flow_params(levels=levels, sweeps_per_pass=k, tile_variant=variant))
             assert torch.equal(f, ref), (variant, k)
     (f,) = scn.flow([job], scn.flow_params(levels=levels))
