@@ -939,6 +939,18 @@ struct JacobiChoice {
   int32_t bands = 0;  // streaming variants: row bands per pair (0: sized from the pair count)
 };
 
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    cached[dev] = (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) ? n : 256;
+  }
+  return cached[dev];
+}
+
 bool variant_fits(int v, int32_t k, const LevelGeom& g) {
   if (v == 0) return k == 1;
   if (kVariants[v].rows == 0) return k >= 1 && k <= kVariants[v].waves && kVariants[v].waves <= g.w &&
@@ -993,7 +1005,10 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     // LDS, so that 8 waves (two workgroups) fit a CU's 160 KiB up to K = 13;
     // larger K run one wave per workgroup (6 or 7 per CU).
     const int wb = K <= 13 ? 4 : 1;
-    const int64_t grid = (units + wb - 1) / wb;
+    int64_t grid = (units + wb - 1) / wb;
+    // a list walk runs on a resident grid (8 waves per CU): the waves stride
+    // over the units, and an empty list costs one short launch
+    if (c.act_list) grid = std::min<int64_t>(grid, (int64_t)device_cus() * (8 / wb));
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     const dim3 gd((unsigned)grid), bd(64 * wb);
     if (K == 10 && v.prefetch == 6) {
@@ -1216,10 +1231,12 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       const int64_t tpp = (int64_t)tiles_x * tiles_y;
       if (tpp * ch.n_pairs > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
       KernelTimer timer("hs_setup", s);
-      // with an active-pair list the grid covers about one pair in eight and
-      // the workgroups stride over the list (as the streaming Jacobi does)
+      // with an active-pair list the grid covers about one pair in eight, at
+      // most four workgroups per CU, and the workgroups stride over the list
+      // (as the streaming Jacobi does)
       const int64_t n_grid = c.act_list ? std::max<int64_t>(1, (ch.n_pairs + 7) / 8) : ch.n_pairs;
-      const dim3 grid((unsigned)(tpp * n_grid));
+      const int64_t blocks = c.act_list ? std::min<int64_t>(tpp * n_grid, 4LL * device_cus()) : tpp * n_grid;
+      const dim3 grid((unsigned)blocks);
       const bool u8 = g.level == 0, co = g.has_coarse != 0;
       auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, c, g, coarse, start_dst, alpha2, tiles_x, (int32_t)tpp);

@@ -615,20 +615,83 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
   }
 }
 
+// conv2 of the fused conv1+conv2 kernel (32 -> 64 channels, stride 2) on an
+// LDS tile of conv1 outputs whose rows store the even columns first and the
+// odd columns after them (HE = (IW + 1) / 2 even columns): a stride-2 tap then
+// reads consecutive stored pixels, 80 bytes apart, so the 16-byte fragment
+// reads of 8 consecutive lanes hit 8 distinct bank groups.  Waves 0..TOH-1
+// compute output channels 0-31 and waves TOH..2 TOH-1 channels 32-63, each
+// wave one output row (TOW / 16 blocks of 16 pixels); the wave's B fragments (9 taps x 2 channel
+// blocks, 72 VGPRs) are loaded once per kernel and stay in registers.  Every
+// accumulator sees the same MFMA sequence as in conv_tile_mma (taps in order,
+// one 32-channel block), so the outputs are bitwise those of that routine.
+template <int TOH, int TOW, int IW>
+__device__ __forceinline__ void conv12_mma(const bf16_t* __restrict__ tile, const bf16x8 (&bw)[9][2],
+                                           const f32x4 (&bb)[2], bf16_t* __restrict__ y, const CGeom& g, int n,
+                                           int oy0, int ox0) {
+  constexpr int CI = 32, CO = 64, CP = CI + 8, HE = (IW + 1) / 2, MR = TOW / 16;
+  static_assert(IW == 2 * TOW + 1, "one output row per wave, TOH waves per channel half");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int orow = wv % TOH, half = wv / TOH;
+  f32x4 acc[MR][2];
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[mr][j] = bb[j];
+  auto load_a = [&](int tap, bf16x8 (&a)[MR]) {
+    const int ky = tap / 3, kx = tap % 3;
+    const bf16_t* rowp = tile + ((2 * orow + ky) * IW) * CP + kg * 8;
+#pragma unroll
+    for (int mr = 0; mr < MR; ++mr) {
+      const int oc = mr * 16 + r16;  // stored column of input column 2 oc + kx
+      a[mr] = ld8(rowp + (kx == 1 ? HE + oc : oc + (kx >> 1)) * CP);
+    }
+  };
+  bf16x8 ab[2][MR];
+  load_a(0, ab[0]);
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    if (tap + 1 < 9) load_a(tap + 1, ab[(tap + 1) & 1]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int mr = 0; mr < MR; ++mr) acc[mr][j] = mfma(bw[tap][j], ab[tap & 1][mr], acc[mr][j]);
+  }
+  char* yimg = reinterpret_cast<char*>(y) + (int64_t)n * g.ho * g.wo * CO * 2;  // wave-uniform
+  const int oy = oy0 + orow;
+  if (oy >= g.ho) return;
+#pragma unroll
+  for (int mr = 0; mr < MR; ++mr) {
+    const int ox = ox0 + mr * 16 + r16;
+    if (ox >= g.wo) continue;
+    const uint32_t mo = (uint32_t)(oy * g.wo + ox) * (uint32_t)(CO * 2);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int co = (2 * half + j) * 16 + 4 * kg;
+      const f32x4 v = acc[mr][j];  // bias included
+      uint2 pk;
+      pk.x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
+      pk.y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
+      typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+      stg32(reinterpret_cast<u32x2_t*>(yimg), mo + 2u * (uint32_t)co, u32x2_t{pk.x, pk.y});
+    }
+  }
+}
+
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
-// persistent kernel.  A workgroup stages conv2's weights (36 KB) in LDS once
-// and then walks conv2 output tiles t, t + gridDim.x, ...  Per tile (TOH x TOW
-// conv2 outputs) it forms the network-input tile (2 channels, zero outside
-// the image) from the two frames' luma, computes the conv1 outputs that
-// conv2's input tile needs straight into LDS (zero outside the image, which
-// is conv2's padding), and runs conv2 from the LDS tile and weights.  conv1's
-// activation never reaches HBM (the unfused pair writes and re-reads it: 64 B
-// per half-res pixel).  The next tile's luma loads are issued before the
-// current tile's conv2 MFMAs and land in the other network-input buffer after
-// them.  conv1 uses the same fragments, MFMA and rounding as k_conv_fwd<0>,
-// so the conv2 input is bitwise the same.  4 x 64 tiles with 8 waves run 15%
-// faster than 4 x 32 (one fewer tile per 256 outputs re-stages half as many
-// halo pixels per output); one workgroup per CU (the LDS holds 138 KB).
+// persistent kernel.  A workgroup loads conv2's weight fragments into VGPRs
+// once and then walks conv2 output tiles t, t + gridDim.x, ...  Per tile
+// (TOH x TOW conv2 outputs) it forms the network-input tile (2 channels, zero
+// outside the image) from the two frames' luma, computes the conv1 outputs
+// that conv2's input tile needs straight into LDS (zero outside the image,
+// which is conv2's padding), and runs conv2 from the LDS tile (conv12_mma).
+// conv1's activation never reaches HBM (the unfused pair writes and re-reads
+// it: 64 B per half-res pixel).  The next tile's luma loads are issued before
+// the current tile's conv2 MFMAs and land in the other network-input buffer
+// after them.  conv1 uses the same fragments, MFMA and rounding as
+// k_conv_fwd<0>, so the conv2 input is bitwise the same.  4 x 64 tiles with 8
+// waves; one workgroup per CU (the LDS holds 104 KB).
 template <int TOH, int TOW, int NWAVE>
 __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restrict__ frames,
                                                         const PairDesc* __restrict__ pairs,
@@ -638,11 +701,11 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
   constexpr int IH = 2 * TOH + 1, IW = 2 * TOW + 1, CP = 32 + 8;  // conv2 input tile = conv1 outputs
   constexpr int XH = IH + 2, XW = IW + 2;                          // net-input tile
   constexpr int NT = 64 * NWAVE;
-  static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].stride == 2, "layer shapes");
-  constexpr int W2 = 9 * 64 * 32;  // conv2's forward weights [tap][co][ci]
+  static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].co == 64 &&
+                kNet[1].stride == 2 && NWAVE == 2 * TOH, "layer shapes");
+  constexpr int HE = (IW + 1) / 2;  // stored even columns of a tile row (conv12_mma)
   __shared__ uint32_t xt[2][XH * XW];  // two bf16 channels per pixel, double-buffered
   __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
-  __shared__ __attribute__((aligned(16))) bf16_t wlds[W2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
   constexpr int NX = XH * XW, ITX = (NX + NT - 1) / NT;
@@ -690,20 +753,21 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
   f32x4 bv[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) bv[nb] = bias4(b1, nb * 16 + 4 * kg);
+  // conv2's B fragments of this wave's two channel blocks ([tap][co][ci] in
+  // the blob) and their biases
+  bf16x8 bw2[9][2];
+  f32x4 bb2[2];
   {
-    constexpr int NW8 = W2 / 8, WIT = (NW8 + NT - 1) / NT;
-    const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(1));
-    uint4 wreg[WIT];
+    const bf16_t* wf2 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
 #pragma unroll
-    for (int i = 0; i < WIT; ++i) wreg[i] = wsrc[min(tid + i * NT, NW8 - 1)];
-    load_x(t);
+    for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-    for (int i = 0; i < WIT; ++i) {
-      const int c = tid + i * NT;  // 16-byte chunk c8 of weight row r (conv2: CI = 32)
-      if (c < NW8) *reinterpret_cast<uint4*>(wlds + WSwz<32>::off(c / 4, c % 4)) = wreg[i];
-    }
-    store_x(xt[0]);
+      for (int j = 0; j < 2; ++j) bw2[tap][j] = ld8(wf2 + (tap * 64 + (2 * (wv / TOH) + j) * 16 + r16) * 32 + kg * 8);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bb2[j] = bias4(b2, (2 * (wv / TOH) + j) * 16 + 4 * kg);
   }
+  load_x(t);
+  store_x(xt[0]);
   __syncthreads();
   // per lane: the xt offsets of its four taps (lane group kg covers taps
   // 4kg .. 4kg+3 of K = 18 = 9 taps x 2 channels; taps >= 9 are zero)
@@ -744,13 +808,13 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restri
           pk.x = relu_bf16x2(pack_bf16x2(acc[0], acc[1]));
           pk.y = relu_bf16x2(pack_bf16x2(acc[2], acc[3]));
         }
-        if (pidx < NPX) *reinterpret_cast<uint2*>(tile + pi * CP + co) = pk;
+        if (pidx < NPX) *reinterpret_cast<uint2*>(tile + (py * IW + ((px & 1) ? HE + (px >> 1) : px >> 1)) * CP + co) = pk;
       }
     }
     __syncthreads();
     const int tn = t + gridDim.x;
     if (tn < n_tiles) load_x(tn);  // in flight during this tile's conv2 MFMAs
-    conv_tile_mma<1, TOH, TOW, NWAVE, IH, IW, true>(tile, wlds, b2, y, g2, n, oy0, ox0);
+    conv12_mma<TOH, TOW, IW>(tile, bw2, bb2, y, g2, n, oy0, ox0);
     if (tn < n_tiles) store_x(xt[buf ^ 1]);  // that buffer was last read before the barrier above
     __syncthreads();  // the next tile's conv1 overwrites the tile conv2 just read
   }
