@@ -1198,7 +1198,7 @@ __global__ void k_net_input(const FrameDesc* __restrict__ frames, const PairDesc
 
 // pixels per thread of the fused upsample + gate kernel (4 ran no faster:
 // more waves per SIMD, but 16% more VALU work per pixel)
-constexpr int kGatePx = 8;
+constexpr int kGateGX = 2, kGateGY = 1, kGatePx = 4 * kGateGX * kGateGY;
 
 // Bilinear x2 upsampling tap (half-pixel centres, clamped).
 struct UpTap {
@@ -1366,106 +1366,101 @@ __global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float*
 // Full-resolution flow of the network (x2 bilinear of the half-resolution
 // output, written to the pair's output) fused with the gate statistic
 // |I2(x + w) - I1(x)| (clamped bilinear warp of luma), reduced per block.
-template <int PX>
+template <int GX, int GY>
 __global__ void __launch_bounds__(256) k_up_gate(const float* __restrict__ half, const FrameDesc* __restrict__ frames,
                                                  const PairDesc* __restrict__ pairs, float* __restrict__ part,
                                                  int32_t h, int32_t w, int32_t blocks_per_pair) {
-  // each thread: PX (4 or 8) consecutive pixels of one row (W is a multiple of 8)
-  static_assert(PX == 4 || PX == 8, "pixels per thread");
+  // Each thread: GX x GY groups of 4 consecutive pixels, the groups W / GX
+  // columns and H / GY rows apart (W is a multiple of 4 GX, H of GY), so that
+  // the 16-byte flow stores of consecutive threads cover consecutive memory
+  // and each thread has GX GY independent groups of loads in flight.
+  static_assert(GX >= 1 && GX <= 2 && GY >= 1 && GY <= 2, "groups per thread");
   __shared__ float red[4];
   const int32_t W = 2 * w, H = 2 * h;
+  const int32_t TPR = W / (4 * GX), RPG = H / GY;  // threads per row, rows per row group
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t p = blk / blocks_per_pair;
-  const int32_t q = (blk % blocks_per_pair) * 256 + threadIdx.x;  // PX-pixel group
+  const int32_t q = (blk % blocks_per_pair) * 256 + threadIdx.x;
   float r = 0.f;
-  if (q < (W / PX) * H) {
-    const int32_t y = q / (W / PX), xb = (q % (W / PX)) * PX;
+  if (q < TPR * RPG) {
+    const int32_t yq = q / TPR, t = q % TPR;
     const PairDesc pd = pairs[p];
     const FrameDesc f1 = frames[pd.f1], f2 = frames[pd.f2];
     const float* hp = half + p * (int64_t)h * w * 2;
     const uint8_t* a = f2.y;
     const uint32_t p2 = (uint32_t)f2.pitch;
-    const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
-    // the first frame's PX luma bytes in one load where the row is aligned
-    uint8_t y1v[PX];
-    if (((reinterpret_cast<uintptr_t>(f1.y) | (uintptr_t)f1.pitch) & (PX - 1)) == 0) {
-      if constexpr (PX == 8) {
-        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-        const u32x2_t v8 = ldg32(reinterpret_cast<const u32x2_t*>(row1), (uint32_t)xb);
+    const bool al4 = ((reinterpret_cast<uintptr_t>(f1.y) | (uintptr_t)f1.pitch) & 3) == 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          y1v[k] = (uint8_t)(v8.x >> (8 * k));
-          y1v[4 + k] = (uint8_t)(v8.y >> (8 * k));
-        }
-      } else {
+    for (int gi = 0; gi < GX * GY; ++gi) {
+      const int32_t xb = 4 * t + (gi % GX) * (W / GX), y = yq + (gi / GX) * RPG;
+      const uint8_t* row1 = f1.y + y * (int32_t)f1.pitch;
+      const UpTap ty = up_tap(y, h);
+      const uint32_t o_u = 4u * (uint32_t)(y * W), o_v = o_u + 4u * (uint32_t)(W * H);  // byte offsets of the row
+      // the first frame's 4 luma bytes in one load where the row is aligned
+      uint8_t y1v[4];
+      if (al4) {
         const uint32_t v4 = ldg32(reinterpret_cast<const uint32_t*>(row1), (uint32_t)xb);
 #pragma unroll
         for (int k = 0; k < 4; ++k) y1v[k] = (uint8_t)(v4 >> (8 * k));
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y1v[k] = ldg32(row1, (uint32_t)(xb + k));
       }
-    } else {
+      // The 4 pixels read half-resolution columns k0 .. k0 + 3 (k0 = xb/2 - 1,
+      // clamped) of two rows: 8 loads instead of 16.  Pixel j's taps (up_tap)
+      // are columns (j+1)/2 and (j+1)/2 + 1 of that window; at the clamped
+      // image borders the tap weight of a substituted column is 0, so the
+      // values equal full_flow_at's.
+      const int32_t k0 = xb / 2 - 1;
+      float2 r0[4], r1[4];
 #pragma unroll
-      for (int k = 0; k < PX; ++k) y1v[k] = ldg32(row1, (uint32_t)(xb + k));
-    }
-    // The PX pixels read half-resolution columns k-1 .. k+PX/2 (k = xb/2,
-    // clamped) of two rows: PX + 4 loads instead of 4 PX.  Pixel j's taps
-    // (up_tap) are columns (j+1)/2 and (j+1)/2 + 1 of that window; at the
-    // clamped image borders the tap weight of a substituted column is 0, so
-    // the values equal full_flow_at's.
-    const UpTap ty = up_tap(y, h);
-    const int32_t k0 = xb / 2 - 1;
-    constexpr int NCOL = PX / 2 + 2;
-    float2 r0[NCOL], r1[NCOL];
+      for (int c = 0; c < 4; ++c) {
+        const int32_t col = min(max(k0 + c, 0), w - 1);
+        const f32x2_t t0 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i0 * (uint32_t)w + (uint32_t)col));
+        const f32x2_t t1 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i1 * (uint32_t)w + (uint32_t)col));
+        r0[c] = make_float2(t0.x, t0.y);
+        r1[c] = make_float2(t1.x, t1.y);
+      }
+      // Away from the left and right image borders the horizontal taps are
+      // fixed: weights 0.75 / 0.25 for even / odd pixels (exact values of
+      // up_tap there), so the per-pixel tap arithmetic is skipped.
+      const bool interior = xb > 0 && xb + 4 < W;
+      float fu4[4], fv4[4];
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      const int32_t col = min(max(k0 + c, 0), w - 1);
-      const f32x2_t t0 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i0 * (uint32_t)w + (uint32_t)col));
-      const f32x2_t t1 = ldg32(reinterpret_cast<const f32x2_t*>(hp), 8u * ((uint32_t)ty.i1 * (uint32_t)w + (uint32_t)col));
-      r0[c] = make_float2(t0.x, t0.y);
-      r1[c] = make_float2(t1.x, t1.y);
-    }
-    // Away from the left and right image borders the horizontal taps are
-    // fixed: weights 0.75 / 0.25 for even / odd pixels (exact values of
-    // up_tap there), so the per-pixel tap arithmetic is skipped.
-    const bool interior = xb > 0 && xb + PX < W;
-    float fu8[PX], fv8[PX];
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const int32_t x = xb + k;
-      UpTap tx;
-      if (interior) tx.f = (k & 1) ? 0.25f : 0.75f;
-      else tx = up_tap(x, w);
-      constexpr int kIa[8] = {0, 1, 1, 2, 2, 3, 3, 4};
-      const float2 fa = r0[kIa[k]], fb = r0[kIa[k] + 1], fc = r1[kIa[k]], fd = r1[kIa[k] + 1];
-      const float uu = (1.f - ty.f) * ((1.f - tx.f) * fa.x + tx.f * fb.x) + ty.f * ((1.f - tx.f) * fc.x + tx.f * fd.x);
-      const float vv = (1.f - ty.f) * ((1.f - tx.f) * fa.y + tx.f * fb.y) + ty.f * ((1.f - tx.f) * fc.y + tx.f * fd.y);
-      const float2 f = make_float2(2.f * uu, 2.f * vv);
-      fu8[k] = f.x;
-      fv8[k] = f.y;
-      const float fu = floorf(f.x), fv = floorf(f.y);
-      int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
-      float fx = f.x - fu, fy = f.y - fv;
-      // Columns: the two samples of a row come from one 2-byte load at
-      // xs = clamp(xi, 0, W - 2) (unaligned global loads are allowed).  Past
-      // the right edge the clamped sample is the second byte with weight 1,
-      // which equals the first byte with weight 0 of the plain clamped form.
-      int32_t xs;
-      if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= W - 1) { xs = W - 2; fx = 1.f; } else { xs = xi; }
-      if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
-      const int32_t y1 = min(yi + 1, H - 1);
-      // rows < 2^15, pitch <= 2^20 (checked on the host): 24-bit products
-      const uint32_t o0 = __umul24((uint32_t)yi, p2), o1 = __umul24((uint32_t)y1, p2);
-      const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(a), o0 + (uint32_t)xs);
-      const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(a), o1 + (uint32_t)xs);
-      const float top = (1.f - fx) * (float)(w0 & 0xFFu) + fx * (float)(w0 >> 8);
-      const float bot = (1.f - fx) * (float)(w1 & 0xFFu) + fx * (float)(w1 >> 8);
-      r += fabsf((1.f - fy) * top + fy * bot - (float)y1v[k]);
-    }
-    float* ou = pd.out + (int64_t)y * W + xb;
-    float* ov = ou + (int64_t)W * H;
-#pragma unroll
-    for (int k = 0; k < PX; k += 4) {
-      *reinterpret_cast<float4*>(ou + k) = make_float4(fu8[k], fu8[k + 1], fu8[k + 2], fu8[k + 3]);
-      *reinterpret_cast<float4*>(ov + k) = make_float4(fv8[k], fv8[k + 1], fv8[k + 2], fv8[k + 3]);
+      for (int k = 0; k < 4; ++k) {
+        const int32_t x = xb + k;
+        UpTap tx;
+        if (interior) tx.f = (k & 1) ? 0.25f : 0.75f;
+        else tx = up_tap(x, w);
+        constexpr int kIa[4] = {0, 1, 1, 2};
+        const float2 fa = r0[kIa[k]], fb = r0[kIa[k] + 1], fc = r1[kIa[k]], fd = r1[kIa[k] + 1];
+        const float uu = (1.f - ty.f) * ((1.f - tx.f) * fa.x + tx.f * fb.x) + ty.f * ((1.f - tx.f) * fc.x + tx.f * fd.x);
+        const float vv = (1.f - ty.f) * ((1.f - tx.f) * fa.y + tx.f * fb.y) + ty.f * ((1.f - tx.f) * fc.y + tx.f * fd.y);
+        const float2 f = make_float2(2.f * uu, 2.f * vv);
+        fu4[k] = f.x;
+        fv4[k] = f.y;
+        const float fu = floorf(f.x), fv = floorf(f.y);
+        int32_t xi = x + (int32_t)fu, yi = y + (int32_t)fv;
+        float fx = f.x - fu, fy = f.y - fv;
+        // Columns: the two samples of a row come from one 2-byte load at
+        // xs = clamp(xi, 0, W - 2) (unaligned global loads are allowed).  Past
+        // the right edge the clamped sample is the second byte with weight 1,
+        // which equals the first byte with weight 0 of the plain clamped form.
+        int32_t xs;
+        if (xi < 0) { xs = 0; fx = 0.f; } else if (xi >= W - 1) { xs = W - 2; fx = 1.f; } else { xs = xi; }
+        if (yi < 0) { yi = 0; fy = 0.f; } else if (yi >= H - 1) { yi = H - 1; fy = 0.f; }
+        const int32_t y1 = min(yi + 1, H - 1);
+        // rows < 2^15, pitch <= 2^20 (checked on the host): 24-bit products
+        const uint32_t o0 = __umul24((uint32_t)yi, p2), o1 = __umul24((uint32_t)y1, p2);
+        const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(a), o0 + (uint32_t)xs);
+        const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(a), o1 + (uint32_t)xs);
+        const float top = (1.f - fx) * (float)(w0 & 0xFFu) + fx * (float)(w0 >> 8);
+        const float bot = (1.f - fx) * (float)(w1 & 0xFFu) + fx * (float)(w1 >> 8);
+        r += fabsf((1.f - fy) * top + fy * bot - (float)y1v[k]);
+      }
+      typedef float f32x4_t __attribute__((ext_vector_type(4)));
+      stg32(reinterpret_cast<f32x4_t*>(pd.out), o_u + 4u * (uint32_t)xb, f32x4_t{fu4[0], fu4[1], fu4[2], fu4[3]});
+      stg32(reinterpret_cast<f32x4_t*>(pd.out), o_v + 4u * (uint32_t)xb, f32x4_t{fv4[0], fv4[1], fv4[2], fv4[3]});
     }
   }
   // wave reduction, then across the four waves (fixed order: deterministic)
@@ -1879,7 +1874,7 @@ scn_status launch_up_gate(const float* half, const FrameDesc* frames, const Pair
   const int32_t W = 2 * d.w, H = 2 * d.h;
   const int32_t bpp = (int32_t)(((int64_t)(W / kGatePx) * H + 255) / 256);
   KernelTimer timer("gate", s);
-  hipLaunchKernelGGL(k_up_gate<kGatePx>, dim3((unsigned)(bpp * n)), dim3(256), 0, s, half, frames, pairs, part, d.h,
+  hipLaunchKernelGGL((k_up_gate<kGateGX, kGateGY>), dim3((unsigned)(bpp * n)), dim3(256), 0, s, half, frames, pairs, part, d.h,
                      d.w, bpp);
   SCN_LAUNCHED("upsample + gate launch");
   hipLaunchKernelGGL(k_gate_final, dim3((unsigned)n), dim3(256), 0, s, part, bpp,
