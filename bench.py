@@ -482,6 +482,37 @@ def c3_workload(scn, torch, dev, args):
             "per_resolution": per_res}
 
 
+def schedule_sweep(scn, torch, dev, jobs, flows):
+    """Per-level Jacobi time of the 1080p step under explicit schedules (Jacobi
+    kernel variant, sweeps per pass): every schedule gives the same bits, so
+    this isolates where a pass is bound.  A pass of k sweeps moves the same
+    bytes for any k, so a pass time that stays flat as k grows means the pass
+    is bound by memory, one that grows with k by instruction issue."""
+    out = []
+    ref = None
+    for v, k in [(9, 10), (15, 13), (16, 13), (6, 8), (5, 6), (17, 17)]:
+        prm = scn.flow_params(LEVELS, ALPHA, ITERS, sweeps_per_pass=k, tile_variant=v)
+        ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, jobs, prm), dtype=torch.uint8, device=dev)
+        scn.flow(jobs, prm, outs=flows, ws=ws)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = [f.clone() for f in flows]
+        same = all(torch.equal(a, b) for a, b in zip(ref, flows))
+        scn.timing_enable(True, 1 << 16)
+        scn.timing_reset()
+        for _ in range(3):
+            scn.flow(jobs, prm, outs=flows, ws=ws)
+        torch.cuda.synchronize()
+        lv = {l: scn.timing_read("hs_jacobi_l%d" % l) for l in range(LEVELS)}
+        scn.timing_enable(False)
+        passes = (ITERS + k - 1) // k
+        out.append({"variant": v, "sweeps_per_pass": k, "passes": passes, "bitwise_equal_to_first": same,
+                    "jacobi_ms_per_step": {l: lv[l][0] / 3 for l in lv},
+                    "level0_ms_per_pass": lv[0][0] / 3 / passes})
+        del ws
+    return out
+
+
 def c5_workload(scn, torch, dev, args):
     """Camera rig: 14 cameras x 300 time steps at 2048x2048 (rows t*14 + c), flow
     of the 13 neighbouring-camera pairs per time step (RANGE windows of 14 rows),
@@ -897,6 +928,8 @@ def main():
     ap.add_argument("--warm-iters", type=int, default=10, help="--workload c3: iterations of a warm pair")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for HBM traffic)")
+    ap.add_argument("--schedule-sweep", action="store_true",
+                    help="only time the step's Jacobi levels under explicit schedules (sweeps per pass 6..17)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the pixel stage has no multi-GPU path "
@@ -939,6 +972,10 @@ def main():
     ws_hist = [torch.empty(scn.workspace_bytes(scn.SCN_OP_HIST, [j]), dtype=torch.uint8, device=dev) for j in jobs]
     ws_flow = torch.empty(scn.workspace_bytes(scn.SCN_OP_FLOW, jobs, prm), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    if args.schedule_sweep:
+        for line in schedule_sweep(scn, torch, dev, jobs, flows):
+            print(json.dumps(line))
+        return
 
     def step():
         for j, h, w in zip(jobs, hists, ws_hist):
