@@ -91,6 +91,28 @@ def _jacobi_timing(scn):
     return ms, n
 
 
+def _jacobi_units(scn):
+    """Pixel-passes (level pixels x pairs, per pass over the planes) of the
+    recorded Jacobi launches, summed over the per-level classes."""
+    return sum(scn.timing_units("hs_jacobi_l%d" % lv) for lv in range(7))
+
+
+def _jacobi_roofline(jac_ms, jac_n, units, px_sweeps, traffic=None):
+    """HBM roofline of the Jacobi launches (28 B per pixel and pass: u, v, a,
+    b, c read and u, v written once, whatever the sweeps per pass), with the
+    FP32 ALU view (27 FLOP per pixel-sweep) beside it."""
+    comp = 28.0 * units
+    gbs = comp / (jac_ms * 1e-3) / 1e9
+    tfl = FLOP_PER_PX_SWEEP * px_sweeps / (jac_ms * 1e-3) / 1e12
+    return {"kernel": "hs_jacobi", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": comp / max(jac_n, 1),
+            "algorithmic_unit": "28 B per pixel and pass (level pixels x pairs per launch)",
+            "launches": jac_n, "avg_launch_ms": jac_ms / max(jac_n, 1),
+            "alu": {"achieved_TFLOPs": tfl, "flop_per_px_sweep": FLOP_PER_PX_SWEEP, "px_sweeps": px_sweeps,
+                    "peak_TFLOPs": FP32_PEAK_TFLOPS, "frac": tfl / FP32_PEAK_TFLOPS}}
+
+
 def _read_tune_cache():
     path = os.environ.get("SCN_TUNE_CACHE")
     if not path or not os.path.exists(path):
@@ -425,6 +447,7 @@ def c3_workload(scn, torch, dev, args):
     scn.timing_reset()
     dt_eager = _timed_calls(torch, calls, args.steps, 0)
     jac_ms, jac_n = _jacobi_timing(scn)
+    jac_units = _jacobi_units(scn)
     hist_ms, _ = scn.timing_read("hist16")
     scn.timing_enable(False)
     # the whole step (4 x (16 HIST + one flow call)) captured once, replayed
@@ -462,10 +485,8 @@ def c3_workload(scn, torch, dev, args):
         pr = sum(scn.count_pairs(jobs[(r, k)]) for k in range(C3_STREAMS_PER_RES))
         per_res["%dx%d" % (w, h)] = {"frames_per_s": fr / t, "pairs_per_s": pr / t,
                                       "latency_s_per_window": t / C3_STREAMS_PER_RES, "s_per_pass": t}
-    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * args.steps / (jac_ms * 1e-3) / 1e12
-    roof = {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None}
-    if warm:  # the pixel-sweep count above assumes every pair solved cold
+    roof = _jacobi_roofline(jac_ms, jac_n, jac_units, px_sweeps * args.steps)
+    if warm:  # warm pairs run masked passes (no unit count) and fewer sweeps
         roof = None
     return {"metric": "frames/s through HIST + flow, 64 uneven streams (C3)", "value": frames / dt,
             "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
@@ -550,12 +571,13 @@ def c5_workload(scn, torch, dev, args):
     scn.timing_enable(True, 1 << 20)
     scn.timing_reset()
     _timed_calls(torch, calls, args.steps, 0)
-    jac_ms, _ = _jacobi_timing(scn)
+    jac_ms, jac_n = _jacobi_timing(scn)
+    jac_units = _jacobi_units(scn)
     scn.timing_enable(False)
     pairs = sum(scn.count_pairs(j) for j in jobs)
     frames = cams * steps_t
     px_sweeps = pairs * _px_levels(S, S, levels) * ITERS
-    jac_tflops = FLOP_PER_PX_SWEEP * px_sweeps * args.steps / (jac_ms * 1e-3) / 1e12
+    roof = _jacobi_roofline(jac_ms, jac_n, jac_units, px_sweeps * args.steps)
     # surrogate + gated fallback on the same calls (trained on 512x384 layered scenes)
     sur = None
     from paper_1805_07339_amd import train as T
@@ -591,8 +613,7 @@ def c5_workload(scn, torch, dev, args):
                        "frames_per_step": frames, "pairs_per_step": pairs, "resident_nv12_GB": rows.numel() / 1e9,
                        "workspace_GB": ws_bytes / 2 ** 30, "generation_s": gen_s},
             "pairs_per_s": pairs / dt,
-            "roofline": {"kernel": "hs_jacobi", "bound": "alu", "achieved": jac_tflops, "peak": FP32_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": jac_tflops / FP32_PEAK_TFLOPS, "traffic": None},
+            "roofline": roof,
             "surrogate": sur}
 
 
@@ -1007,6 +1028,7 @@ def main():
     torch.cuda.synchronize()
     kern = {k: scn.timing_read(k) for k in ["hist16", "pyr_down", "hs_setup", "hs_jacobi"] +
             ["hs_jacobi_l%d" % l for l in range(LEVELS)]}
+    jac_units = _jacobi_units(scn)  # pixel-passes of the timed Jacobi launches
     scn.timing_enable(False)
 
     # --- algorithmic work of the dominant kernel (Jacobi) -------------------
@@ -1024,8 +1046,7 @@ def main():
     # compulsory HBM bytes of the Jacobi launches: one launch runs one pass
     # (up to K sweeps) over a level and must read u, v, a, b, c and write u, v
     # once per pixel (28 B), whatever K is
-    jac_compulsory = sum(28.0 * w * h * p_total * kern["hs_jacobi_l%d" % l][1] / args.steps
-                         for l, (w, h) in enumerate(lv)) * args.steps
+    jac_compulsory = 28.0 * jac_units
     jac_comp_gbs = jac_compulsory / (jac_ms * 1e-3) / 1e9
     hist_ms_step, hist_n_step = kern["hist16"]
 

@@ -364,6 +364,15 @@ scn_status scn_flow_surrogate(const scn_job* jobs, int32_t n_jobs, const scn_flo
 scn_status scn_timing_enable(int32_t enable, int32_t max_launches);
 scn_status scn_timing_reset(void);
 scn_status scn_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+/* Summed work units of the recorded launches of one kernel class (same
+ * classes and pool as scn_timing_read; no synchronisation).  The Jacobi
+ * classes ("hs_jacobi", "hs_jacobi_l*") record, per pass over the planes
+ * of a chunk, the level's pixels x the chunk's pairs, whatever the pass's
+ * sweep count (every launch of the one-sweep schedule is a pass; a masked
+ * fallback pass, whose pair count is known only on the device, records 0);
+ * other classes record 0.  *units receives the sum;
+ * SCN_EINVAL for NULL arguments, SCN_ENOSPACE if launches were dropped. */
+scn_status scn_timing_units(const char* kernel, double* units);
 
 /* Drop the record of the last plan uploaded to `ws` (for example before the
  * memory is freed; a capture on `ws` is then refused until an eager call). */

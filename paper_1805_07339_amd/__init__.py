@@ -62,7 +62,7 @@ class CFlowParams(ctypes.Structure):
 # Every symbol declared in include/scn.h (checked by the CPU test suite).
 EXPORTS = ["scn_count_rows", "scn_count_pairs", "scn_workspace_bytes", "scn_sample_convert", "scn_hist",
            "scn_hist_diff", "scn_space_map", "scn_flow", "scn_ws_forget", "scn_last_error", "scn_version", "scn_timing_enable",
-           "scn_timing_reset", "scn_timing_read", "scn_net_bytes", "scn_net_params", "scn_net_pack",
+           "scn_timing_reset", "scn_timing_read", "scn_timing_units", "scn_net_bytes", "scn_net_params", "scn_net_pack",
            "scn_adam_step", "scn_surrogate_grads", "scn_surrogate_infer", "scn_flow_surrogate", "scn_hist_static",
            "scn_surrogate_train_step"]
 
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.scn_timing_reset.restype = ctypes.c_int
     L.scn_timing_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]
     L.scn_timing_read.restype = ctypes.c_int
+    L.scn_timing_units.argtypes = [ctypes.c_char_p, P(ctypes.c_double)]
+    L.scn_timing_units.restype = ctypes.c_int
     L.scn_net_bytes.argtypes = []
     L.scn_net_bytes.restype = ctypes.c_size_t
     L.scn_net_params.argtypes = []
@@ -547,6 +549,13 @@ def timing_read(kernel: str) -> Tuple[float, int]:
     n = ctypes.c_int64()
     _check(lib().scn_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def timing_units(kernel: str) -> float:
+    """Summed work units recorded for one kernel class (Jacobi: pixels x pairs per pass)."""
+    u = ctypes.c_double()
+    _check(lib().scn_timing_units(kernel.encode(), ctypes.byref(u)))
+    return u.value
 
 
 def version() -> str:

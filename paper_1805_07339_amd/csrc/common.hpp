@@ -37,7 +37,7 @@ void forget_plan(const void* ws);
 // in a KernelTimer are bracketed by HIP events recorded on their stream.
 // Events come from a pool created when timing is enabled.
 bool timing_on();
-int timing_begin(const char* name, hipStream_t s);   // returns a record id or -1
+int timing_begin(const char* name, hipStream_t s, double units = 0.0);  // returns a record id or -1
 void timing_end(int id, hipStream_t s);
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
@@ -55,7 +55,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
 struct KernelTimer {
   int id;
   hipStream_t s;
-  KernelTimer(const char* name, hipStream_t st) : id(timing_on() ? timing_begin(name, st) : -1), s(st) {}
+  // `units`: work units of the launch (the Jacobi passes record pixels x
+  // pairs, so that a benchmark can form algorithmic bytes per launch)
+  KernelTimer(const char* name, hipStream_t st, double units = 0.0)
+      : id(timing_on() ? timing_begin(name, st, units) : -1), s(st) {}
   ~KernelTimer() {
     if (id >= 0) timing_end(id, s);
   }

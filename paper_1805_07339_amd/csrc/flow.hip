@@ -963,8 +963,12 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
                          int32_t src, int32_t dst, int32_t ns, hipStream_t s) {
   static constexpr const char* kLevelTimer[] = {"hs_jacobi_l0", "hs_jacobi_l1", "hs_jacobi_l2", "hs_jacobi_l3",
                                                 "hs_jacobi_l4", "hs_jacobi_l5", "hs_jacobi_l6"};
-  KernelTimer timer("hs_jacobi", s);
-  KernelTimer timer_l(kLevelTimer[std::min(g.level, 6)], s);
+  // work units: pixels of the level x pairs per pass over the planes (each
+  // launch of the one-sweep kernel is a pass; 0 for a masked pass, whose pair
+  // count is known only on the device)
+  const double units = c.active ? 0.0 : (double)g.w * g.h * (double)n_pairs * (jc.variant == 0 ? ns : 1);
+  KernelTimer timer("hs_jacobi", s, units);
+  KernelTimer timer_l(kLevelTimer[std::min(g.level, 6)], s, units);
   if (jc.variant == 0) {
     const int64_t bpp = ((int64_t)g.w * g.h + kThreads - 1) / kThreads;
     for (int32_t it = 0; it < ns; ++it) {

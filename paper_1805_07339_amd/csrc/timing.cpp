@@ -13,6 +13,7 @@ namespace {
 struct Rec {
   std::string name;
   int ev0, ev1;
+  double units;
 };
 std::mutex g_mu;
 bool g_on = false;
@@ -31,14 +32,14 @@ void destroy_pool() {
 
 bool timing_on() { return g_on; }
 
-int timing_begin(const char* name, hipStream_t s) {
+int timing_begin(const char* name, hipStream_t s, double units) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return -1;
   if (g_next + 2 > g_pool.size()) {
     ++g_dropped;
     return -1;
   }
-  Rec r{name, (int)g_next, (int)g_next + 1};
+  Rec r{name, (int)g_next, (int)g_next + 1, units};
   g_next += 2;
   if (hipEventRecord(g_pool[r.ev0], s) != hipSuccess) return -1;
   g_recs.push_back(r);
@@ -107,6 +108,24 @@ scn_status scn_timing_read(const char* kernel, double* total_ms, int64_t* launch
   }
   *total_ms = tot;
   *launches = n;
+  if (g_dropped) {
+    set_error("timing pool exhausted; some launches were not recorded");
+    return SCN_ENOSPACE;
+  }
+  return SCN_OK;
+}
+
+scn_status scn_timing_units(const char* kernel, double* units) {
+  clear_error();
+  if (!kernel || !units) {
+    set_error("NULL argument");
+    return SCN_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  double u = 0.0;
+  for (const Rec& r : g_recs)
+    if (r.name == kernel) u += r.units;
+  *units = u;
   if (g_dropped) {
     set_error("timing pool exhausted; some launches were not recorded");
     return SCN_ENOSPACE;

@@ -248,6 +248,32 @@ def test_jacobi_schedules_are_bitwise_identical(w, h, levels):
     assert torch.equal(f, ref)
 
 
+def test_timing_units_count_pixel_passes():
+    """The Jacobi timers' work units are the level's pixels x the pairs of
+    every pass over the planes (the benchmark forms algorithmic bytes per
+    launch from them): 5 passes of 10 sweeps on the streaming kernel, 50
+    one-sweep launches on the reference schedule."""
+    need_gpu()
+    w, h, levels = 160, 120, 3
+    frames, _ = c1_frames(n=3, w=w, h=h, seed=3)
+    tab = table_from_frames(frames, 3, [0, 1, 2], w, h)
+    job = scn.Job(scn.Table.from_tensor(tab, w, h), scn.Sampling.stride(1, 0, 3))
+    sizes = [(160, 120), (80, 60), (40, 30)]
+    for variant, k, passes in ((9, 10, 5), (0, 1, 50)):
+        p = scn.flow_params(levels=levels, sweeps_per_pass=k, tile_variant=variant)
+        scn.flow([job], p)
+        torch.cuda.synchronize()
+        scn.timing_enable(True, 4096)
+        scn.timing_reset()
+        scn.flow([job], p)
+        torch.cuda.synchronize()
+        for lv, (lw, lh) in enumerate(sizes):
+            assert scn.timing_units("hs_jacobi_l%d" % lv) == lw * lh * 2 * passes, (variant, lv)
+        assert scn.timing_units("hs_jacobi") == sum(lw * lh for lw, lh in sizes) * 2 * passes
+        assert scn.timing_units("hs_setup") == 0
+        scn.timing_enable(False)
+
+
 @pytest.mark.parametrize("warm", [0, 2])
 def test_graph_capture_replays_match_eager(warm):
     """After one eager call (plan upload, tuning), the flow and HIST calls of an
