@@ -27,6 +27,12 @@ DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-co
                 "-munsafe-fp-atomics", "-Wno-unused-command-line-argument"]
 
 
+# Per-file flags: MFMA results in VGPRs rather than AGPRs for the
+# convolution kernels (the fused conv1+conv2 kernel reads every conv1 MFMA
+# result back for BF16 packing; with AGPR results each costs a copy).
+FILE_FLAGS = {"surrogate.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip")))
 
@@ -41,7 +47,7 @@ def _run(cmd):
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     path = os.path.join(CSRC, src)
-    cmd = [HIPCC] + DEVICE_FLAGS + ["-I", INCLUDE, "-I", CSRC]
+    cmd = [HIPCC] + DEVICE_FLAGS + FILE_FLAGS.get(src, []) + ["-I", INCLUDE, "-I", CSRC]
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", path, "-o", obj]

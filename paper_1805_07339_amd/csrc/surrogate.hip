@@ -9,6 +9,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -615,208 +616,214 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
   }
 }
 
-// conv2 of the fused conv1+conv2 kernel (32 -> 64 channels, stride 2) on an
-// LDS tile of conv1 outputs whose rows store the even columns first and the
-// odd columns after them (HE = (IW + 1) / 2 even columns): a stride-2 tap then
-// reads consecutive stored pixels, 80 bytes apart, so the 16-byte fragment
-// reads of 8 consecutive lanes hit 8 distinct bank groups.  Waves 0..TOH-1
-// compute output channels 0-31 and waves TOH..2 TOH-1 channels 32-63, each
-// wave one output row (TOW / 16 blocks of 16 pixels); the wave's B fragments (9 taps x 2 channel
-// blocks, 72 VGPRs) are loaded once per kernel and stay in registers.  Every
-// accumulator sees the same MFMA sequence as in conv_tile_mma (taps in order,
-// one 32-channel block), so the outputs are bitwise those of that routine.
-template <int TOH, int TOW, int IW>
-__device__ __forceinline__ void conv12_mma(const bf16_t* __restrict__ tile, const bf16x8 (&bw)[9][2],
-                                           const f32x4 (&bb)[2], bf16_t* __restrict__ y, const CGeom& g, int n,
-                                           int oy0, int ox0) {
-  constexpr int CI = 32, CO = 64, CP = CI + 8, HE = (IW + 1) / 2, MR = TOW / 16;
-  static_assert(IW == 2 * TOW + 1, "one output row per wave, TOH waves per channel half");
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r16 = lane & 15, kg = lane >> 4;
-  const int orow = wv % TOH, half = wv / TOH;
-  f32x4 acc[MR][2];
-#pragma unroll
-  for (int mr = 0; mr < MR; ++mr)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[mr][j] = bb[j];
-  auto load_a = [&](int tap, bf16x8 (&a)[MR]) {
-    const int ky = tap / 3, kx = tap % 3;
-    const bf16_t* rowp = tile + ((2 * orow + ky) * IW) * CP + kg * 8;
-#pragma unroll
-    for (int mr = 0; mr < MR; ++mr) {
-      const int oc = mr * 16 + r16;  // stored column of input column 2 oc + kx
-      a[mr] = ld8(rowp + (kx == 1 ? HE + oc : oc + (kx >> 1)) * CP);
-    }
-  };
-  bf16x8 ab[2][MR];
-  load_a(0, ab[0]);
-#pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    if (tap + 1 < 9) load_a(tap + 1, ab[(tap + 1) & 1]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int mr = 0; mr < MR; ++mr) acc[mr][j] = mfma(bw[tap][j], ab[tap & 1][mr], acc[mr][j]);
-  }
-  char* yimg = reinterpret_cast<char*>(y) + (int64_t)n * g.ho * g.wo * CO * 2;  // wave-uniform
-  const int oy = oy0 + orow;
-  if (oy >= g.ho) return;
-#pragma unroll
-  for (int mr = 0; mr < MR; ++mr) {
-    const int ox = ox0 + mr * 16 + r16;
-    if (ox >= g.wo) continue;
-    const uint32_t mo = (uint32_t)(oy * g.wo + ox) * (uint32_t)(CO * 2);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int co = (2 * half + j) * 16 + 4 * kg;
-      const f32x4 v = acc[mr][j];  // bias included
-      uint2 pk;
-      pk.x = relu_bf16x2(pack_bf16x2(v[0], v[1]));
-      pk.y = relu_bf16x2(pack_bf16x2(v[2], v[3]));
-      typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-      stg32(reinterpret_cast<u32x2_t*>(yimg), mo + 2u * (uint32_t)co, u32x2_t{pk.x, pk.y});
-    }
-  }
-}
-
 // Inference: conv1 (2 -> 32, stride 1) and conv2 (32 -> 64, stride 2) in one
-// persistent kernel.  A workgroup loads conv2's weight fragments into VGPRs
-// once and then walks conv2 output tiles t, t + gridDim.x, ...  Per tile
-// (TOH x TOW conv2 outputs) it forms the network-input tile (2 channels, zero
-// outside the image) from the two frames' luma, computes the conv1 outputs
-// that conv2's input tile needs straight into LDS (zero outside the image,
-// which is conv2's padding), and runs conv2 from the LDS tile (conv12_mma).
-// conv1's activation never reaches HBM (the unfused pair writes and re-reads
-// it: 64 B per half-res pixel).  The next tile's luma loads are issued before
-// the current tile's conv2 MFMAs and land in the other network-input buffer
-// after them.  conv1 uses the same fragments, MFMA and rounding as
-// k_conv_fwd<0>, so the conv2 input is bitwise the same.  4 x 64 tiles with 8
-// waves; one workgroup per CU (the LDS holds 104 KB).
-template <int TOH, int TOW, int NWAVE>
-__global__ void __launch_bounds__(64 * NWAVE) k_conv12(const FrameDesc* __restrict__ frames,
-                                                        const PairDesc* __restrict__ pairs,
-                                                        const uint8_t* __restrict__ blob, bf16_t* __restrict__ y,
-                                                        CGeom g1, CGeom g2, int32_t tiles_x, int32_t tiles_per_img,
-                                                        int32_t n_tiles) {
-  constexpr int IH = 2 * TOH + 1, IW = 2 * TOW + 1, CP = 32 + 8;  // conv2 input tile = conv1 outputs
-  constexpr int XH = IH + 2, XW = IW + 2;                          // net-input tile
-  constexpr int NT = 64 * NWAVE;
+// persistent kernel without an LDS tile of conv1 outputs.  A wave owns a
+// strip of 64 conv2 output columns (4 blocks of 16 pixels) and a band of
+// output rows and streams down it.  Per output row and conv2 tap, the conv1
+// outputs the tap reads (each block's 16 pixels, two apart) are computed
+// straight into conv2's fragment layout: conv1's weight rows are taken in the
+// order 0-3, 8-11, 16-19, 24-27 for the first 16-row MFMA block and 4-7,
+// 12-15, 20-23, 28-31 for the second, so that lane (r16, kg) ends with
+// channels 8kg .. 8kg + 7 of its pixel -- the eight BF16 values conv2's
+// fragment needs -- after the same bias, rounding and ReLU as the
+// standalone conv1 (zero outside the image: conv2's padding).  A conv1
+// output is recomputed by each conv2 tap that reads it (2.25 on average):
+// the price of no LDS round trip and no barrier.  The network input (2x2
+// luma means of both frames in BF16, the arithmetic of k_net_input) of the
+// strip's rows sits in a per-wave ring of 8 rows in LDS; the two rows the
+// next output row needs are loaded during the current row's MFMAs.  conv2's
+// weights are staged in LDS once per workgroup.  Every output sees the MFMA
+// sequence of the unfused layers (conv1: one K block; conv2: taps in order,
+// one 32-channel block), so the results are bitwise theirs.
+constexpr int kC12sCols = 64;                      // conv2 output columns per strip
+constexpr int kC12sRing = 8;                       // network-input rows per wave ring
+constexpr int kC12sRW = 2 * kC12sCols + 4;         // ring row stride (2 * 64 + 3 columns used)
+template <int NWAVE, int BAND>
+__global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restrict__ frames,
+                                                         const PairDesc* __restrict__ pairs,
+                                                         const uint8_t* __restrict__ blob, bf16_t* __restrict__ y,
+                                                         CGeom g1, CGeom g2, int32_t strips, int32_t bands,
+                                                         int64_t units) {
   static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].co == 64 &&
-                kNet[1].stride == 2 && NWAVE == 2 * TOH, "layer shapes");
-  constexpr int HE = (IW + 1) / 2;  // stored even columns of a tile row (conv12_mma)
-  __shared__ uint32_t xt[2][XH * XW];  // two bf16 channels per pixel, double-buffered
-  __shared__ __attribute__((aligned(16))) bf16_t tile[IH * IW * CP];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+                kNet[1].stride == 2, "layer shapes");
+  constexpr int NT = 64 * NWAVE, W2 = 9 * 64 * 32, NCOL = 2 * kC12sCols + 3;
+  // [wave][row slot][column]: two bf16 channels; slot kC12sRing stays zero
+  // (the reads of conv1's padded K elements, taps 9 .. 11, point there)
+  __shared__ uint32_t ring[NWAVE][kC12sRing + 1][kC12sRW];
+  __shared__ __attribute__((aligned(16))) bf16_t w2[W2];  // conv2 weights [tap][co][ci], swizzled rows
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r16 = lane & 15, kg = lane >> 4;
-  constexpr int NX = XH * XW, ITX = (NX + NT - 1) / NT;
-  uint32_t xr[ITX];
-  // network input of tile t into xr: per half-resolution pixel the 2x2 luma
-  // mean (round half up) as (v - 128) / 64 in BF16, channel 0 = first frame
-  // (the arithmetic of k_net_input); (v - 128) / 64 with integer v is exact
-  // in BF16, so the hardware pack returns the same bits
-  auto load_x = [&](int t) {
-    const int n = t / tiles_per_img, r = t % tiles_per_img;
-    const int xy0 = 2 * (r / tiles_x) * TOH - 2, xx0 = 2 * (r % tiles_x) * TOW - 2;
-    const PairDesc pd = pairs[n];
-    const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
-    const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
-#pragma unroll
-    for (int i = 0; i < ITX; ++i) {
-      const int e = min(tid + i * NT, NX - 1);
-      const int yy = xy0 + e / XW, xx = xx0 + e % XW;
-      const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx < g1.wi;
-      const uint32_t ry = 2u * (uint32_t)(ok ? yy : 0), rx = 2u * (uint32_t)(ok ? xx : 0);
-      auto sum4 = [&](const uint8_t* yp, uint32_t pitch) -> int {
-        const uint32_t w0 = ldg32(reinterpret_cast<const uint16_t*>(yp), ry * pitch + rx);
-        const uint32_t w1 = ldg32(reinterpret_cast<const uint16_t*>(yp), (ry + 1) * pitch + rx);
-        return (int)((w0 & 0xFFu) + (w0 >> 8) + (w1 & 0xFFu) + (w1 >> 8));
-      };
-      const int s1 = sum4(fa.y, pa), s2 = sum4(fb.y, pbp);
-      const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
-                                     (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
-      xr[i] = ok ? v : 0u;
-    }
-  };
-  auto store_x = [&](uint32_t* buf) {
-#pragma unroll
-    for (int i = 0; i < ITX; ++i)
-      if (tid + i * NT < NX) buf[tid + i * NT] = xr[i];
-  };
-  int t = xcd_block(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;  // uniform over the workgroup, before any barrier
+  {
+    const uint4* wsrc = reinterpret_cast<const uint4*>(blob + blob_fwd_off(1));
+    for (int c = tid; c < W2 / 8; c += NT) *reinterpret_cast<uint4*>(w2 + WSwz<32>::off(c / 4, c % 4)) = wsrc[c];
+  }
+  for (int c = lane; c < kC12sRW; c += 64) ring[wv][kC12sRing][c] = 0u;
+  __syncthreads();  // the only barrier: waves are independent from here on
   const bf16_t* wf1 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(0));
   const float* b1 = reinterpret_cast<const float*>(blob + blob_bias_off(0));
   const float* b2 = reinterpret_cast<const float*>(blob + blob_bias_off(1));
-  bf16x8 bw[2];
+  // conv1 fragments in the permuted row order, and their biases
+  bf16x8 bw1[2];
+  f32x4 bv1[2];
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) bw[nb] = ld8(wf1 + (nb * 16 + r16) * 32 + kg * 8);
-  f32x4 bv[2];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) bv[nb] = bias4(b1, nb * 16 + 4 * kg);
-  // conv2's B fragments of this wave's two channel blocks ([tap][co][ci] in
-  // the blob) and their biases
-  bf16x8 bw2[9][2];
-  f32x4 bb2[2];
-  {
-    const bf16_t* wf2 = reinterpret_cast<const bf16_t*>(blob + blob_fwd_off(1));
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bw2[tap][j] = ld8(wf2 + (tap * 64 + (2 * (wv / TOH) + j) * 16 + r16) * 32 + kg * 8);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) bb2[j] = bias4(b2, (2 * (wv / TOH) + j) * 16 + 4 * kg);
+  for (int j = 0; j < 2; ++j) {
+    bw1[j] = ld8(wf1 + (8 * (r16 >> 2) + 4 * j + (r16 & 3)) * 32 + kg * 8);
+    bv1[j] = bias4(b1, 8 * kg + 4 * j);
   }
-  load_x(t);
-  store_x(xt[0]);
-  __syncthreads();
-  // per lane: the xt offsets of its four taps (lane group kg covers taps
-  // 4kg .. 4kg+3 of K = 18 = 9 taps x 2 channels; taps >= 9 are zero)
-  int toff[4];
+  // lane group kg covers conv1's K elements 8kg .. 8kg+7 = taps 4kg .. 4kg+3
+  // of the 3x3 window, two channels each (taps >= 9 are zero)
+  int tdy[4], cbase[4];
+  bool tok[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int tap = 4 * kg + j;
-    toff[j] = tap < 9 ? (tap / 3) * XW + tap % 3 : -1;
+    tok[j] = tap < 9;
+    tdy[j] = tok[j] ? tap / 3 : 0;
+    cbase[j] = 2 * r16 + (tok[j] ? tap % 3 : 0);  // ring column of the tap for block 0, kx = 0
   }
-  constexpr int NPX = IH * IW, NBK = (NPX + 15) / 16, NIT = (NBK + NWAVE - 1) / NWAVE;
-  for (int buf = 0; t < n_tiles; t += gridDim.x, buf ^= 1) {
-    const int n = t / tiles_per_img, r = t % tiles_per_img;
-    const int oy0 = (r / tiles_x) * TOH, ox0 = (r % tiles_x) * TOW;
-    const int cy0 = 2 * oy0 - 1, cx0 = 2 * ox0 - 1;  // conv1-output coordinates of tile (0, 0)
-    const uint32_t* xb = xt[buf];
+  uint32_t(&rg)[kC12sRing + 1][kC12sRW] = ring[wv];
+  const uint32_t* rflat = &ring[wv][0][0];
+  const int64_t per_pair = (int64_t)bands * strips;
+  for (int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NWAVE + wv; unit < units;
+       unit += (int64_t)gridDim.x * NWAVE) {
+    const int n = (int)(unit / per_pair);
+    const int rem = (int)(unit % per_pair);
+    const int band = rem / strips, sx = rem % strips;
+    const int ox0 = sx * kC12sCols, oy_a = band * BAND, oy_b = min(g2.ho, oy_a + BAND);
+    const int xb = 2 * ox0 - 2;                                      // network-input column of ring column 0
+    const PairDesc pd = pairs[n];
+    const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
+    const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
+    // network-input row yy of the strip: lane l takes columns 2l, 2l + 1
+    // (one 4-byte load per luma row and frame covers both pixels' 2x2 blocks)
+    // and lanes 0, 1 also columns 128 + 2l, 129 + 2l; then the BF16 pairs go
+    // into the ring (the arithmetic of k_net_input; zero outside the image)
+    auto load_row = [&](int yy, uint32_t (&lw)[2][4]) {
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int blk = wv + it * NWAVE;
-      if (blk >= NBK) break;
-      const int pidx = blk * 16 + r16;
-      const int pi = min(pidx, NPX - 1);
-      const int py = pi / IW, px = pi % IW;
-      uint4 pw;
-      const int pb = py * XW + px;
-      pw.x = toff[0] >= 0 ? xb[pb + toff[0]] : 0u;
-      pw.y = toff[1] >= 0 ? xb[pb + toff[1]] : 0u;
-      pw.z = toff[2] >= 0 ? xb[pb + toff[2]] : 0u;
-      pw.w = toff[3] >= 0 ? xb[pb + toff[3]] : 0u;
-      const bf16x8 a = __builtin_bit_cast(bf16x8, pw);
-      const int cy = cy0 + py, cx = cx0 + px;
-      const bool inside = cy >= 0 && cy < g1.ho && cx >= 0 && cx < g1.wo;
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const f32x4 acc = mfma(bw[nb], a, bv[nb]);
-        const int co = nb * 16 + 4 * kg;
-        uint2 pk = make_uint2(0u, 0u);
-        if (inside) {
-          pk.x = relu_bf16x2(pack_bf16x2(acc[0], acc[1]));
-          pk.y = relu_bf16x2(pack_bf16x2(acc[2], acc[3]));
+      for (int i = 0; i < 2; ++i) {
+        const int c = i == 0 ? 2 * lane : min(128 + 2 * lane, NCOL - 1), xx = xb + c;
+        const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx + 1 < g1.wi;  // both pixels inside
+        const uint32_t ry = 2u * (uint32_t)(yy >= 0 && yy < g1.hi ? yy : 0);
+        const uint32_t rx = 2u * (uint32_t)(ok ? xx : 0);
+        if (i == 0 || lane < 2) {
+          lw[i][0] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), ry * pa + rx);
+          lw[i][1] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), (ry + 1) * pa + rx);
+          lw[i][2] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), ry * pbp + rx);
+          lw[i][3] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), (ry + 1) * pbp + rx);
         }
-        if (pidx < NPX) *reinterpret_cast<uint2*>(tile + (py * IW + ((px & 1) ? HE + (px >> 1) : px >> 1)) * CP + co) = pk;
       }
+    };
+    auto store_row = [&](int yy, const uint32_t (&lw)[2][4]) {
+      const bool yok = yy >= 0 && yy < g1.hi;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i == 1 && lane >= 2) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // pixel c + h: bytes 2h, 2h + 1 of each loaded word
+          const int c = (i == 0 ? 2 * lane : 128 + 2 * lane) + h, xx = xb + c;
+          const bool ok = yok && xx >= 0 && xx < g1.wi;
+          const int s1 = (int)(((lw[i][0] >> (16 * h)) & 0xFFu) + ((lw[i][0] >> (16 * h + 8)) & 0xFFu) +
+                               ((lw[i][1] >> (16 * h)) & 0xFFu) + ((lw[i][1] >> (16 * h + 8)) & 0xFFu));
+          const int s2 = (int)(((lw[i][2] >> (16 * h)) & 0xFFu) + ((lw[i][2] >> (16 * h + 8)) & 0xFFu) +
+                               ((lw[i][3] >> (16 * h)) & 0xFFu) + ((lw[i][3] >> (16 * h + 8)) & 0xFFu));
+          const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
+                                         (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
+          if (c < NCOL) rg[yy & (kC12sRing - 1)][c] = ok ? v : 0u;
+        }
+      }
+    };
+    for (int r = 0; r < 5; r += 2) {  // the band's first five rows, two at a time
+      uint32_t lw[2][2][4];
+      load_row(2 * oy_a - 2 + r, lw[0]);
+      if (r + 1 < 5) load_row(2 * oy_a - 1 + r, lw[1]);
+      store_row(2 * oy_a - 2 + r, lw[0]);
+      if (r + 1 < 5) store_row(2 * oy_a - 1 + r, lw[1]);
     }
-    __syncthreads();
-    const int tn = t + gridDim.x;
-    if (tn < n_tiles) load_x(tn);  // in flight during this tile's conv2 MFMAs
-    conv12_mma<TOH, TOW, IW>(tile, bw2, bb2, y, g2, n, oy0, ox0);
-    if (tn < n_tiles) store_x(xt[buf ^ 1]);  // that buffer was last read before the barrier above
-    __syncthreads();  // the next tile's conv1 overwrites the tile conv2 just read
+    // strips at the left or right image border hold conv1 columns outside
+    // the image, and output row 0 reads conv1 row -1: those rows take the
+    // path that zeroes such conv1 outputs (conv2's padding)
+    const bool col_edge = xb + 1 < 0 || xb + 1 + 2 * kC12sCols + 1 >= g1.wo;
+    for (int oy = oy_a; oy < oy_b; ++oy) {
+      // the two network-input rows of the next output row, in flight during this row's MFMAs
+      uint32_t nx[2][2][4];
+      load_row(2 * oy + 3, nx[0]);
+      load_row(2 * oy + 4, nx[1]);
+      f32x4 acc[4][4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const f32x4 bias = bias4(b2, nb * 16 + 4 * kg);
+#pragma unroll
+        for (int mr = 0; mr < 4; ++mr) acc[mr][nb] = bias;
+      }
+      // word offsets of tap j's ring row for tap row ky of conv2 (the zero row
+      // for conv1's padded K elements); block mr and tap column kx add
+      // 32 mr + kx, a constant of the read instruction
+      int roff[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+          roff[j][ky] = tok[j] ? ((2 * oy - 2 + ky + tdy[j]) & (kC12sRing - 1)) * kC12sRW + cbase[j]
+                               : kC12sRing * kC12sRW;
+      auto taps = [&](auto edge) {
+        constexpr bool EDGE = decltype(edge)::value;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int ky = t / 3, kx = t % 3;
+          bf16x8 bq[4];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) bq[nb] = ld8(w2 + WSwz<32>::off(t * 64 + nb * 16 + r16, kg));
+          const int cy = 2 * oy - 1 + ky;  // conv1 output row of this tap (wave-uniform)
+#pragma unroll
+          for (int mr = 0; mr < 4; ++mr) {
+            uint4 pw;
+            pw.x = rflat[roff[0][ky] + 32 * mr + kx];
+            pw.y = rflat[roff[1][ky] + 32 * mr + kx];
+            pw.z = rflat[roff[2][ky] + 32 * mr + kx];
+            pw.w = rflat[roff[3][ky] + 32 * mr + kx];
+            const bf16x8 a1 = __builtin_bit_cast(bf16x8, pw);
+            const f32x4 d0 = mfma(bw1[0], a1, bv1[0]);
+            const f32x4 d1 = mfma(bw1[1], a1, bv1[1]);
+            uint4 pk;
+            pk.x = relu_bf16x2(pack_bf16x2(d0[0], d0[1]));
+            pk.y = relu_bf16x2(pack_bf16x2(d0[2], d0[3]));
+            pk.z = relu_bf16x2(pack_bf16x2(d1[0], d1[1]));
+            pk.w = relu_bf16x2(pack_bf16x2(d1[2], d1[3]));
+            if constexpr (EDGE) {
+              const int cx = xb + 1 + 2 * (mr * 16 + r16) + kx;  // conv1 output column
+              if (cy < 0 || cy >= g1.ho || cx < 0 || cx >= g1.wo) pk = make_uint4(0u, 0u, 0u, 0u);
+            }
+            const bf16x8 a2 = __builtin_bit_cast(bf16x8, pk);
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[mr][nb] = mfma(bq[nb], a2, acc[mr][nb]);
+          }
+          // keep each tap's fragment reads with its MFMAs (hoisting every tap's
+          // reads ahead would hold 9 x 16 fragment registers)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      };
+      if (col_edge || oy == 0) taps(std::true_type{});
+      else taps(std::false_type{});
+      char* yimg = reinterpret_cast<char*>(y) + (int64_t)n * g2.ho * g2.wo * 64 * 2;  // wave-uniform
+#pragma unroll
+      for (int mr = 0; mr < 4; ++mr) {
+        const int ox = ox0 + mr * 16 + r16;
+        if (ox >= g2.wo) continue;
+        const uint32_t mo = (uint32_t)(oy * g2.wo + ox) * (uint32_t)(64 * 2);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const f32x4 v = acc[mr][nb];  // bias included
+          typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+          stg32(reinterpret_cast<u32x2_t*>(yimg), mo + 2u * (uint32_t)(nb * 16 + 4 * kg),
+                u32x2_t{relu_bf16x2(pack_bf16x2(v[0], v[1])), relu_bf16x2(pack_bf16x2(v[2], v[3]))});
+        }
+      }
+      // rows 2oy+3, 2oy+4 take the slots of rows 2oy-5, 2oy-4, which no
+      // tap of this output row read (a wave's LDS operations run in order)
+      store_row(2 * oy + 3, nx[0]);
+      store_row(2 * oy + 4, nx[1]);
+    }
   }
 }
 
@@ -1771,24 +1778,23 @@ scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float
   return SCN_OK;
 }
 
-// Fused conv1 + conv2: output tile, waves per workgroup, workgroups per CU.
-constexpr int kConv12TOH = 4, kConv12TOW = 64, kConv12NW = 8, kConv12PerCu = 1;
+// Fused conv1 + conv2 (streaming): waves per workgroup, output rows per band,
+// workgroups per CU (8-row bands balance the last round of waves better
+// than 16- or 32-row ones; 4-row bands pay the five-row start too often).
+constexpr int kC12sNW = 4, kC12sBand = 8, kC12sPerCu = 2;
 
 scn_status launch_conv12(const FrameDesc* frames, const PairDesc* pairs, const uint8_t* blob, bf16_t* y,
-                          const NetDims& d, int64_t n, hipStream_t s) {
-  constexpr int TOH = kConv12TOH, TOW = kConv12TOW, NW = kConv12NW;
+                         const NetDims& d, int64_t n, hipStream_t s) {
   const CGeom g1 = layer_geom(d, 0, n), g2 = layer_geom(d, 1, n);
-  const int32_t tx = (g2.wo + TOW - 1) / TOW, ty = (g2.ho + TOH - 1) / TOH;
-  const int64_t tiles = (int64_t)tx * ty * n;
-  if (tiles > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
-  // one workgroup per resident slot
+  const int32_t strips = (g2.wo + kC12sCols - 1) / kC12sCols, bands = (g2.ho + kC12sBand - 1) / kC12sBand;
+  const int64_t units = (int64_t)strips * bands * n;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * kConv12PerCu);
+  const int64_t grid = std::min<int64_t>((units + kC12sNW - 1) / kC12sNW, (int64_t)cus * kC12sPerCu);
   KernelTimer timer("conv_fwd", s);
   KernelTimer timer_l("conv_fwd12", s);
-  hipLaunchKernelGGL((k_conv12<TOH, TOW, NW>), dim3((unsigned)grid), dim3(64 * NW), 0, s, frames, pairs, blob, y, g1,
-                     g2, tx, tx * ty, (int32_t)tiles);
+  hipLaunchKernelGGL((k_conv12s<kC12sNW, kC12sBand>), dim3((unsigned)grid), dim3(64 * kC12sNW), 0, s, frames, pairs,
+                     blob, y, g1, g2, strips, bands, units);
   SCN_LAUNCHED("fused conv1 + conv2 launch");
   return SCN_OK;
 }
