@@ -635,9 +635,10 @@ __global__ void __launch_bounds__(256) k_conv_s2_pers(const bf16_t* __restrict__
 // weights are staged in LDS once per workgroup.  Every output sees the MFMA
 // sequence of the unfused layers (conv1: one K block; conv2: taps in order,
 // one 32-channel block), so the results are bitwise theirs.
-constexpr int kC12sCols = 64;                      // conv2 output columns per strip
+constexpr int kC12sCols = 64;                      // conv2 output columns computed per strip (4 blocks)
+constexpr int kC12sStep = 62;                      // of which stored: strips overlap by 2 columns
 constexpr int kC12sRing = 8;                       // network-input rows per wave ring
-constexpr int kC12sRW = 2 * kC12sCols + 4;         // ring row stride (2 * 64 + 3 columns used)
+constexpr int kC12sRW = 2 * kC12sCols + 4;         // ring row stride (2 * 64 + 3 columns read)
 template <int NWAVE, int BAND>
 __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restrict__ frames,
                                                          const PairDesc* __restrict__ pairs,
@@ -646,7 +647,8 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
                                                          int64_t units) {
   static_assert(kNet[0].ci == 2 && kNet[0].co == 32 && kNet[1].ci == 32 && kNet[1].co == 64 &&
                 kNet[1].stride == 2, "layer shapes");
-  constexpr int NT = 64 * NWAVE, W2 = 9 * 64 * 32, NCOL = 2 * kC12sCols + 3;
+  constexpr int NT = 64 * NWAVE, W2 = 9 * 64 * 32, NCOL = 2 * kC12sStep + 3;
+  static_assert(NCOL <= 128, "one pair of network-input columns per lane");
   // [wave][row slot][column]: two bf16 channels; slot kC12sRing stays zero
   // (the reads of conv1's padded K elements, taps 9 .. 11, point there)
   __shared__ uint32_t ring[NWAVE][kC12sRing + 1][kC12sRW];
@@ -690,51 +692,44 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
     const int n = (int)(unit / per_pair);
     const int rem = (int)(unit % per_pair);
     const int band = rem / strips, sx = rem % strips;
-    const int ox0 = sx * kC12sCols, oy_a = band * BAND, oy_b = min(g2.ho, oy_a + BAND);
+    const int ox0 = sx * kC12sStep, oy_a = band * BAND, oy_b = min(g2.ho, oy_a + BAND);
     const int xb = 2 * ox0 - 2;                                      // network-input column of ring column 0
     const PairDesc pd = pairs[n];
     const FrameDesc fa = frames[pd.f1], fb = frames[pd.f2];
     const uint32_t pa = (uint32_t)fa.pitch, pbp = (uint32_t)fb.pitch;
-    // network-input row yy of the strip: lane l takes columns 2l, 2l + 1
-    // (one 4-byte load per luma row and frame covers both pixels' 2x2 blocks)
-    // and lanes 0, 1 also columns 128 + 2l, 129 + 2l; then the BF16 pairs go
-    // into the ring (the arithmetic of k_net_input; zero outside the image)
-    auto load_row = [&](int yy, uint32_t (&lw)[2][4]) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int c = i == 0 ? 2 * lane : min(128 + 2 * lane, NCOL - 1), xx = xb + c;
-        const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx + 1 < g1.wi;  // both pixels inside
-        const uint32_t ry = 2u * (uint32_t)(yy >= 0 && yy < g1.hi ? yy : 0);
-        const uint32_t rx = 2u * (uint32_t)(ok ? xx : 0);
-        if (i == 0 || lane < 2) {
-          lw[i][0] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), ry * pa + rx);
-          lw[i][1] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), (ry + 1) * pa + rx);
-          lw[i][2] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), ry * pbp + rx);
-          lw[i][3] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), (ry + 1) * pbp + rx);
-        }
-      }
+    // network-input row yy of the strip: lane l takes columns 2l, 2l + 1 (one
+    // 4-byte load per luma row and frame covers both pixels' 2x2 blocks);
+    // then the BF16 pairs go into the ring (the arithmetic of k_net_input;
+    // zero outside the image).  Ring columns NCOL .. 130, read only for the
+    // two computed outputs past kC12sStep, which are not stored, keep stale
+    // values.
+    auto load_row = [&](int yy, uint32_t (&lw)[4]) {
+      const int c = 2 * lane, xx = xb + c;
+      const bool ok = yy >= 0 && yy < g1.hi && xx >= 0 && xx + 1 < g1.wi;  // both pixels inside
+      const uint32_t ry = 2u * (uint32_t)(yy >= 0 && yy < g1.hi ? yy : 0);
+      const uint32_t rx = 2u * (uint32_t)(ok ? xx : 0);
+      lw[0] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), ry * pa + rx);
+      lw[1] = ldg32(reinterpret_cast<const uint32_t*>(fa.y), (ry + 1) * pa + rx);
+      lw[2] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), ry * pbp + rx);
+      lw[3] = ldg32(reinterpret_cast<const uint32_t*>(fb.y), (ry + 1) * pbp + rx);
     };
-    auto store_row = [&](int yy, const uint32_t (&lw)[2][4]) {
+    auto store_row = [&](int yy, const uint32_t (&lw)[4]) {
       const bool yok = yy >= 0 && yy < g1.hi;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        if (i == 1 && lane >= 2) break;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {  // pixel c + h: bytes 2h, 2h + 1 of each loaded word
-          const int c = (i == 0 ? 2 * lane : 128 + 2 * lane) + h, xx = xb + c;
-          const bool ok = yok && xx >= 0 && xx < g1.wi;
-          const int s1 = (int)(((lw[i][0] >> (16 * h)) & 0xFFu) + ((lw[i][0] >> (16 * h + 8)) & 0xFFu) +
-                               ((lw[i][1] >> (16 * h)) & 0xFFu) + ((lw[i][1] >> (16 * h + 8)) & 0xFFu));
-          const int s2 = (int)(((lw[i][2] >> (16 * h)) & 0xFFu) + ((lw[i][2] >> (16 * h + 8)) & 0xFFu) +
-                               ((lw[i][3] >> (16 * h)) & 0xFFu) + ((lw[i][3] >> (16 * h + 8)) & 0xFFu));
-          const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
-                                         (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
-          if (c < NCOL) rg[yy & (kC12sRing - 1)][c] = ok ? v : 0u;
-        }
+      for (int h = 0; h < 2; ++h) {  // pixel 2l + h: bytes 2h, 2h + 1 of each loaded word
+        const int c = 2 * lane + h, xx = xb + c;
+        const bool ok = yok && xx >= 0 && xx < g1.wi;
+        const int s1 = (int)(((lw[0] >> (16 * h)) & 0xFFu) + ((lw[0] >> (16 * h + 8)) & 0xFFu) +
+                             ((lw[1] >> (16 * h)) & 0xFFu) + ((lw[1] >> (16 * h + 8)) & 0xFFu));
+        const int s2 = (int)(((lw[2] >> (16 * h)) & 0xFFu) + ((lw[2] >> (16 * h + 8)) & 0xFFu) +
+                             ((lw[3] >> (16 * h)) & 0xFFu) + ((lw[3] >> (16 * h + 8)) & 0xFFu));
+        const uint32_t v = pack_bf16x2((float)(((s1 + 2) >> 2) - 128) * (1.f / 64.f),
+                                       (float)(((s2 + 2) >> 2) - 128) * (1.f / 64.f));
+        if (c < NCOL) rg[yy & (kC12sRing - 1)][c] = ok ? v : 0u;
       }
     };
     for (int r = 0; r < 5; r += 2) {  // the band's first five rows, two at a time
-      uint32_t lw[2][2][4];
+      uint32_t lw[2][4];
       load_row(2 * oy_a - 2 + r, lw[0]);
       if (r + 1 < 5) load_row(2 * oy_a - 1 + r, lw[1]);
       store_row(2 * oy_a - 2 + r, lw[0]);
@@ -746,7 +741,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
     const bool col_edge = xb + 1 < 0 || xb + 1 + 2 * kC12sCols + 1 >= g1.wo;
     for (int oy = oy_a; oy < oy_b; ++oy) {
       // the two network-input rows of the next output row, in flight during this row's MFMAs
-      uint32_t nx[2][2][4];
+      uint32_t nx[2][4];
       load_row(2 * oy + 3, nx[0]);
       load_row(2 * oy + 4, nx[1]);
       f32x4 acc[4][4];
@@ -766,23 +761,35 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
         for (int ky = 0; ky < 3; ++ky)
           roff[j][ky] = tok[j] ? ((2 * oy - 2 + ky + tdy[j]) & (kC12sRing - 1)) * kC12sRW + cbase[j]
                                : kC12sRing * kC12sRW;
+      auto ring_a = [&](int t, int mr) {  // conv1 fragment of block mr for conv2 tap t
+        const int ky = t / 3, kx = t % 3;
+        uint4 pw;
+        pw.x = rflat[roff[0][ky] + 32 * mr + kx];
+        pw.y = rflat[roff[1][ky] + 32 * mr + kx];
+        pw.z = rflat[roff[2][ky] + 32 * mr + kx];
+        pw.w = rflat[roff[3][ky] + 32 * mr + kx];
+        return pw;
+      };
       auto taps = [&](auto edge) {
         constexpr bool EDGE = decltype(edge)::value;
+        // the ring reads of tap t + 1 are issued before tap t's arithmetic
+        uint4 pw[2][4];
+#pragma unroll
+        for (int mr = 0; mr < 4; ++mr) pw[0][mr] = ring_a(0, mr);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-          const int ky = t / 3, kx = t % 3;
+          const int ky = t / 3, kx = t % 3, cur = t & 1;
           bf16x8 bq[4];
 #pragma unroll
           for (int nb = 0; nb < 4; ++nb) bq[nb] = ld8(w2 + WSwz<32>::off(t * 64 + nb * 16 + r16, kg));
+          if (t + 1 < 9) {
+#pragma unroll
+            for (int mr = 0; mr < 4; ++mr) pw[cur ^ 1][mr] = ring_a(t + 1, mr);
+          }
           const int cy = 2 * oy - 1 + ky;  // conv1 output row of this tap (wave-uniform)
 #pragma unroll
           for (int mr = 0; mr < 4; ++mr) {
-            uint4 pw;
-            pw.x = rflat[roff[0][ky] + 32 * mr + kx];
-            pw.y = rflat[roff[1][ky] + 32 * mr + kx];
-            pw.z = rflat[roff[2][ky] + 32 * mr + kx];
-            pw.w = rflat[roff[3][ky] + 32 * mr + kx];
-            const bf16x8 a1 = __builtin_bit_cast(bf16x8, pw);
+            const bf16x8 a1 = __builtin_bit_cast(bf16x8, pw[cur][mr]);
             const f32x4 d0 = mfma(bw1[0], a1, bv1[0]);
             const f32x4 d1 = mfma(bw1[1], a1, bv1[1]);
             uint4 pk;
@@ -809,7 +816,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
 #pragma unroll
       for (int mr = 0; mr < 4; ++mr) {
         const int ox = ox0 + mr * 16 + r16;
-        if (ox >= g2.wo) continue;
+        if (ox >= g2.wo || mr * 16 + r16 >= kC12sStep) continue;
         const uint32_t mo = (uint32_t)(oy * g2.wo + ox) * (uint32_t)(64 * 2);
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
@@ -1786,7 +1793,7 @@ constexpr int kC12sNW = 4, kC12sBand = 8, kC12sPerCu = 2;
 scn_status launch_conv12(const FrameDesc* frames, const PairDesc* pairs, const uint8_t* blob, bf16_t* y,
                          const NetDims& d, int64_t n, hipStream_t s) {
   const CGeom g1 = layer_geom(d, 0, n), g2 = layer_geom(d, 1, n);
-  const int32_t strips = (g2.wo + kC12sCols - 1) / kC12sCols, bands = (g2.ho + kC12sBand - 1) / kC12sBand;
+  const int32_t strips = (g2.wo + kC12sStep - 1) / kC12sStep, bands = (g2.ho + kC12sBand - 1) / kC12sBand;
   const int64_t units = (int64_t)strips * bands * n;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
