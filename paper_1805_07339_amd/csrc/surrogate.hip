@@ -1167,9 +1167,30 @@ __global__ void __launch_bounds__(64 * NW) k_conv_dw(const void* __restrict__ dy
   if (ky0 == 0 && tid < CO) partb[chunk * CO + tid] = bsum;
 }
 
-// Sum the chunk partials in chunk order into the gradient vector (master
-// layout [co][ci][ky][kx]).  Thread i takes partial index i ([tap][co][ci]
-// order), so that a wave reads consecutive floats of every chunk.
+// Chunk partials are summed in two deterministic stages: groups of
+// kDwGroup consecutive chunks (in place: group g's sum replaces the partial
+// of its first chunk, which only that group reads), then the group sums in
+// group order.  One thread per weight or bias element per stage.
+constexpr int64_t kDwGroup = 32;
+__global__ void k_dw_group(float* __restrict__ part, float* __restrict__ partb, int64_t chunks, int64_t nw,
+                           int32_t co) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.y * kDwGroup, k1 = min(chunks, k0 + kDwGroup);
+  if (i < nw) {
+    float s = 0.f;
+    for (int64_t k = k0; k < k1; ++k) s += part[k * nw + i];
+    part[k0 * nw + i] = s;
+  } else if (i < nw + co) {
+    const int64_t c = i - nw;
+    float s = 0.f;
+    for (int64_t k = k0; k < k1; ++k) s += partb[k * co + c];
+    partb[k0 * co + c] = s;
+  }
+}
+
+// Group sums, in group order, into the gradient vector (master layout
+// [co][ci][ky][kx]).  Thread i takes partial index i ([tap][co][ci] order),
+// so that a wave reads consecutive floats of every group.
 __global__ void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ partb, float* __restrict__ grads,
                             int64_t chunks, int32_t ci, int32_t co, int32_t w_off, int32_t b_off) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1179,12 +1200,12 @@ __global__ void k_dw_reduce(const float* __restrict__ part, const float* __restr
     const int64_t t = i / ci;
     const int c_out = (int)(t % co), tap = (int)(t / co);
     float s = 0.f;
-    for (int64_t k = 0; k < chunks; ++k) s += part[k * nw + i];
+    for (int64_t k = 0; k < chunks; k += kDwGroup) s += part[k * nw + i];
     grads[w_off + ((int64_t)c_out * ci + c_in) * 9 + tap] = s;
   } else if (i < nw + co) {
     const int c_out = (int)(i - nw);
     float s = 0.f;
-    for (int64_t k = 0; k < chunks; ++k) s += partb[k * co + c_out];
+    for (int64_t k = 0; k < chunks; k += kDwGroup) s += partb[k * co + c_out];
     grads[b_off + c_out] = s;
   }
 }
@@ -1778,7 +1799,10 @@ scn_status launch_dw(const void* dy, const bf16_t* x, const NetBuffers& b, float
                        b.partb, g, (int32_t)rpc);
   }
   SCN_LAUNCHED("conv weight-gradient launch");
-  const int64_t n = (int64_t)kNet[L].co * kNet[L].ci * 9 + kNet[L].co;
+  const int64_t nw = (int64_t)kNet[L].co * kNet[L].ci * 9, n = nw + kNet[L].co;
+  hipLaunchKernelGGL(k_dw_group, dim3((unsigned)((n + 255) / 256), (unsigned)((chunks + kDwGroup - 1) / kDwGroup)),
+                     dim3(256), 0, s, b.part, b.partb, chunks, nw, kNet[L].co);
+  SCN_LAUNCHED("weight-gradient group-sum launch");
   hipLaunchKernelGGL(k_dw_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.part, b.partb, grads, chunks,
                      kNet[L].ci, kNet[L].co, param_w_off(L), param_b_off(L));
   SCN_LAUNCHED("weight-gradient reduce launch");
