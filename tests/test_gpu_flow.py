@@ -248,6 +248,28 @@ def test_jacobi_schedules_are_bitwise_identical(w, h, levels):
     assert torch.equal(f, ref)
 
 
+def test_jobs_without_pairs_in_a_batch():
+    """Degenerate jobs -- a single sampled row (no pair), an empty gather and
+    a RANGE of one-row windows -- in one call with a normal job: the call
+    succeeds, the empty jobs get no work and the normal job's flow equals
+    its solo call bit for bit."""
+    need_gpu()
+    frames, _ = c1_frames(n=4, w=96, h=64, seed=5)
+    tab = table_from_frames(frames, 4, [0, 1, 2, 3], 96, 64)
+    t = scn.Table.from_tensor(tab, 96, 64)
+    full = scn.Job(t, scn.Sampling.stride(1, 0, 4))
+    single = scn.Job(t, scn.Sampling.stride(5, 2, 3))
+    empty = scn.Job(t, scn.Sampling.gather([]))
+    ones = scn.Job(t, scn.Sampling.range([(0, 1), (2, 3)]))
+    for j in (single, empty, ones):
+        assert scn.count_pairs(j) == 0
+    p = scn.flow_params(levels=2)
+    (solo,) = scn.flow([full], p)
+    outs = scn.flow([single, full, empty, ones], p)
+    assert [o.shape[0] for o in outs] == [0, 3, 0, 0]
+    assert torch.equal(outs[1], solo)
+
+
 def test_timing_units_count_pixel_passes():
     """The Jacobi timers' work units are the level's pixels x the pairs of
     every pass over the planes (the benchmark forms algorithmic bytes per

@@ -94,6 +94,25 @@ def test_forward_parity(W, H):
         assert r <= REL_FWD
 
 
+def test_jobs_without_pairs_in_a_surrogate_batch():
+    """A job without pairs (one sampled row) beside a normal one: the gated
+    call succeeds, and the normal job's flow equals its solo call bit for
+    bit (gated path and network-only inference)."""
+    need_gpu()
+    tab, job = _pairs_table(64, 48, 3, 17)
+    t = scn.Table.from_tensor(tab, 64, 48)
+    single = scn.Job(t, scn.Sampling.stride(1, 1, 2))
+    assert scn.count_pairs(single) == 0
+    master, _ = _master(_params(4))
+    net = scn.net_pack(master)
+    (solo,) = scn.surrogate_infer([job], net)
+    (f_empty, f_full) = scn.surrogate_infer([single, job], net)
+    assert f_empty.shape[0] == 0 and torch.equal(f_full, solo)
+    flows, fb, res = scn.flow_surrogate([job], net, 1e9)
+    flows2, fb2, res2 = scn.flow_surrogate([single, job], net, 1e9)
+    assert flows2[0].shape[0] == 0 and torch.equal(flows2[1], flows[0]) and torch.equal(res2[1], res[0])
+
+
 def test_forward_persistent_rounds_are_batch_invariant():
     """16 pairs of 512 x 384 give every persistent convolution several rounds
     of tiles per workgroup (conv3: 2, conv4: 3, conv5: 6 on 256 CUs), so the
