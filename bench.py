@@ -305,10 +305,11 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     res = [torch.empty(f.shape[0], dtype=torch.float32, device=dev) for f in plain_flows]
     ws = torch.empty(scn.workspace_bytes(scn.SCN_OP_SURROGATE, jobs, prm), dtype=torch.uint8, device=dev)
 
-    def step():
+    def step(t=None):
         for j, h, w in zip(jobs, hists, ws_hist):
             scn.hist(j, out=h, stream=stream, ws=w)
-        scn.flow_surrogate(jobs, net, tau, prm, outs=outs, fell_back=fbs, residual=res, stream=stream, ws=ws)
+        scn.flow_surrogate(jobs, net, tau if t is None else t, prm, outs=outs, fell_back=fbs, residual=res,
+                           stream=stream, ws=ws)
 
     for _ in range(args.warmup):
         step()
@@ -349,6 +350,7 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
     epe_net = torch.cat([torch.sqrt(((o - p) ** 2).sum(dim=1)).mean(dim=(1, 2)) for o, p in zip(net_only, plain_flows)])
     flops = _conv_flops(W, H) * n_pairs * args.steps
     mfma_tflops = flops / (conv_ms * 1e-3) / 1e12 if conv_ms > 0 else 0.0
+    forced = forced_fallback(scn, torch, step, fbs, res, n_pairs, m_total, dt / args.steps, args)
     return {"value": m_total * args.steps / dt, "unit": "frames/s", "ms_per_step": dt / args.steps * 1e3,
             "tau": tau, "fallback_rate": float(fb.mean()), "mean_epe_vs_plain_px": float(epe.mean()),
             "max_pair_epe_px": float(epe.max()), "network_only_mean_epe_px": float(epe_net.mean()),
@@ -359,7 +361,44 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
                      "flop_per_1080p_pair": _conv_flops(W, H),
                      "per_layer_TFLOPs": layer_tflops,
                      "per_layer_utilisation": {k: v / BF16_PEAK_TFLOPS for k, v in layer_tflops.items()}},
-            "weights": os.path.relpath(path, ROOT), "train_meta": {k: meta[k] for k in meta if k != "loss_history"}}
+            "weights": os.path.relpath(path, ROOT), "train_meta": {k: meta[k] for k in meta if k != "loss_history"},
+            "forced_fallback": forced}
+
+
+def forced_fallback(scn, torch, step, fbs, res, n_pairs, m_total, base_s, args):
+    """The gated step with thresholds below the calibrated one, so that a
+    quarter, a half and all of the pairs fall back: what failing pairs cost at
+    the benchmark shape (the calibrated threshold keeps every pair here).
+    Thresholds are quantiles of the step's own residuals, set just below them
+    so that the pairs at the quantile fall back too."""
+    r = torch.cat([x.float() for x in res]).sort().values
+    out = []
+    for frac in (0.25, 0.5, 1.0):
+        k = n_pairs - int(round(frac * n_pairs))  # pairs kept: the k smallest residuals
+        t = float(r[k].item()) * (1.0 - 1e-6) if k < n_pairs else float("inf")
+        if k == 0:
+            t = 0.0  # every pair with a non-zero residual falls back
+        for _ in range(max(1, args.warmup)):
+            step(t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(t)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        rate = float(torch.cat(fbs).float().mean().item())
+        # the fallback kernels' times from one more pass with the event timers
+        scn.timing_enable(True, 1 << 16)
+        scn.timing_reset()
+        step(t)
+        torch.cuda.synchronize()
+        names = ["pyr_down", "hs_setup"] + ["hs_jacobi_l%d" % l for l in range(LEVELS)]
+        kms = {k: scn.timing_read(k)[0] for k in names}
+        scn.timing_enable(False)
+        out.append({"target_fallback": frac, "fallback_rate": rate, "tau": t, "frames_per_s": m_total / dt,
+                    "ms_per_step": dt * 1e3, "ms_over_no_fallback": (dt - base_s) * 1e3,
+                    "fallback_ms_by_kernel": kms})
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -656,6 +656,37 @@ __device__ __forceinline__ gfloat& at_off(float* base, uint32_t byte_off) {
   return *(gfloat*)((gchar*)base + byte_off);
 }
 
+// Row bands per pair of a streaming Jacobi launch over `n` pairs without a
+// tuned choice: enough waves (`want`) to fill the chip, but no band shorter
+// than 64 rows (each band re-reads a 2K + 3 row halo) or taller than `cap`.
+inline int32_t stream_bands(int32_t h, int32_t strips, int64_t n, int32_t want, int32_t cap) {
+  int64_t bh = (int64_t)h * strips * (n > 1 ? n : 1) / want;
+  bh = bh < 64 ? 64 : (bh > cap ? cap : bh);
+  return (int32_t)((h + bh - 1) / bh);
+}
+
+// Row bands per pair for a walk over a device-built list of `n` pairs by
+// `slots` resident waves: the band count (bands of 4 rows up to `cap`) that
+// minimises rounds of waves x rows a wave streams (band + halo); a wave's
+// rows run one after another, so short bands help when few pairs are
+// listed, and fewer, taller bands re-read less halo when many are.
+// (A heuristic: evaluated in FP32, once per wave.)
+__device__ inline int32_t list_bands(int32_t h, int32_t strips, int64_t n, int32_t slots, int32_t cap, int32_t halo) {
+  const float per_band = (float)strips * (float)(n > 1 ? n : 1) / (float)slots;  // rounds per band of each pair
+  int32_t best = (h + cap - 1) / cap;
+  float best_cost = 3.0e38f;
+  const int32_t b_max = max(best, min(h / 4, 32));
+  for (int32_t b = best; b <= b_max; ++b) {
+    const int32_t bh = (h + b - 1) / b;
+    const float cost = ceilf(per_band * (float)b) * (float)(bh + halo);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = b;
+    }
+  }
+  return best;
+}
+
 template <int K>
 struct StStep {
   float4 (&win)[K][3];
@@ -770,21 +801,31 @@ struct StStep {
 
 template <int K, int P, int WB>
 __global__ void __launch_bounds__(64 * WB) k_hs_jacobi_st(ChunkPtrs c, LevelGeom g, int32_t src_code, int32_t dst_code,
-                                                      int32_t strips, int32_t bands, int32_t band_h) {
+                                                      int32_t strips, int32_t bands, int32_t band_h, int32_t slots,
+                                                      int32_t band_cap) {
   __shared__ float2 ring[WB][K][3][64];  // [wave][row slot][a, b, c][lane] (two columns per lane)
   const int lane = threadIdx.x & 63;
   // wave-uniform from here on: the pair, band, strip, row counters and plane
   // pointers live in SGPRs and their arithmetic runs on the scalar unit
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // With an active-pair list the number of listed pairs is known here only:
+  // the bands are chosen from it (list_bands; `slots` = the grid's waves).
+  int64_t listed = 0;
+  if (c.act_list) {
+    listed = *c.act_count;
+    if (listed == 0) return;
+    bands = list_bands(g.h, strips, listed, slots, band_cap, 2 * K + 3);
+    band_h = (g.h + bands - 1) / bands;
+  }
   const int64_t per_pair = (int64_t)strips * bands;
   // A wave takes unit (pair, band, strip) = its index; with an active-pair
-  // list the units index list slots, and the grid (sized for a fraction of
-  // the pairs) strides over them until the list is exhausted.
+  // list the units index list slots, and the resident grid strides over them
+  // until the list is exhausted.
   for (int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * WB + wv;; unit += (int64_t)gridDim.x * WB) {
     int64_t pr;
     if (c.act_list) {
       const int64_t slot = unit / per_pair;
-      if (slot >= *c.act_count) return;
+      if (slot >= listed) return;
       pr = c.act_list[slot];
     } else {
       pr = unit / per_pair;
@@ -988,41 +1029,43 @@ scn_status launch_jacobi(const JacobiChoice& jc, const ChunkPtrs& c, const Level
     const int32_t K = ns;
     if (K < 1 || K > v.waves) { set_error("internal: bad streaming Jacobi sweep count"); return SCN_EINVAL; }
     const int32_t strips = (g.w + (128 - 2 * K) - 1) / (128 - 2 * K);
-    // bands: enough independent waves to fill the chip (about 24 per CU), but
-    // no band shorter than 64 rows (each band re-reads a 2K + 1 row halo)
-    const int64_t want = 24 * 256;
-    // With an active mask (the surrogate's fallback) only the failing pairs
-    // run and their count is known on the device only; size the bands for
-    // about one pair in eight, so that a small fallback set still fills the
-    // chip (more bands only add waves when more pairs fall back).
+    // bands: enough independent waves to fill the chip (about 24 per CU).
+    // With an active mask but no list (not used by the library's own paths)
+    // the active count is unknown here: bands sized for one pair in eight.
+    // With a list the kernel chooses the bands from the listed count itself.
     const int64_t n_eff = c.active ? std::max<int64_t>(1, (n_pairs + 7) / 8) : n_pairs;
-    int64_t bh = (int64_t)g.h * strips * n_eff / want;
-    bh = std::max<int64_t>(64, std::min<int64_t>(v.band_cap, bh));
+    int32_t bands = stream_bands(g.h, strips, n_eff, 24 * device_cus(), v.band_cap);
     // a tuned band count (the tail of the last round of waves depends on it)
-    if (jc.bands > 0 && !c.active) bh = (g.h + std::min(jc.bands, g.h) - 1) / std::min(jc.bands, g.h);
-    const int32_t bands = (int32_t)((g.h + bh - 1) / bh);
+    if (jc.bands > 0 && !c.active) {
+      const int32_t b = std::min(jc.bands, g.h), bh = (g.h + b - 1) / b;
+      bands = (g.h + bh - 1) / bh;
+    }
     const int32_t band_h = (g.h + bands - 1) / bands;
-    // with an active-pair list the grid covers n_eff pairs' units and the
-    // waves stride over the list (an empty list costs one short launch)
-    const int64_t units = (int64_t)strips * bands * (c.act_list ? n_eff : n_pairs);
+    const int64_t units = (int64_t)strips * bands * n_pairs;
     // Waves per workgroup: each wave's coefficient ring takes K x 1.5 KiB of
     // LDS, so that 8 waves (two workgroups) fit a CU's 160 KiB up to K = 13;
     // larger K run one wave per workgroup (6 or 7 per CU).
     const int wb = K <= 13 ? 4 : 1;
     int64_t grid = (units + wb - 1) / wb;
     // a list walk runs on a resident grid (8 waves per CU): the waves stride
-    // over the units, and an empty list costs one short launch
-    if (c.act_list) grid = std::min<int64_t>(grid, (int64_t)device_cus() * (8 / wb));
+    // over the listed pairs' units, and an empty list costs one short launch
+    if (c.act_list) grid = (int64_t)device_cus() * (8 / wb);
+    const int32_t slots = c.act_list ? (int32_t)(grid * wb) : 0;
     if (grid > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
     const dim3 gd((unsigned)grid), bd(64 * wb);
     if (K == 10 && v.prefetch == 6) {
-      hipLaunchKernelGGL((k_hs_jacobi_st<10, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+      hipLaunchKernelGGL((k_hs_jacobi_st<10, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h, slots,
+                         v.band_cap);
     } else if (K == 12 && v.prefetch == 6) {
-      hipLaunchKernelGGL((k_hs_jacobi_st<12, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h);
+      hipLaunchKernelGGL((k_hs_jacobi_st<12, 6, 4>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h, slots,
+                         v.band_cap);
     } else {
       switch (K) {
 #define SCN_ST(k, wbk) \
-  case k: hipLaunchKernelGGL((k_hs_jacobi_st<k, 3, wbk>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h); break;
+  case k:                                                                                                     \
+    hipLaunchKernelGGL((k_hs_jacobi_st<k, 3, wbk>), gd, bd, 0, s, c, g, src, dst, strips, bands, band_h, slots, \
+                       v.band_cap);                                                                              \
+    break;
         SCN_ST(1, 4) SCN_ST(2, 4) SCN_ST(3, 4) SCN_ST(4, 4) SCN_ST(5, 4) SCN_ST(6, 4) SCN_ST(7, 4) SCN_ST(8, 4)
         SCN_ST(9, 4) SCN_ST(10, 4) SCN_ST(11, 4) SCN_ST(12, 4) SCN_ST(13, 4) SCN_ST(14, 1) SCN_ST(15, 1)
         SCN_ST(16, 1) SCN_ST(17, 1)
@@ -1235,11 +1278,11 @@ scn_status run_flow_chunk(const FlowPlan& plan, const FlowGroup& grp, const Flow
       const int64_t tpp = (int64_t)tiles_x * tiles_y;
       if (tpp * ch.n_pairs > 0x7FFFFFFF) { set_error("flow chunk too large"); return SCN_EUNSUPPORTED; }
       KernelTimer timer("hs_setup", s);
-      // with an active-pair list the grid covers about one pair in eight, at
-      // most four workgroups per CU, and the workgroups stride over the list
-      // (as the streaming Jacobi does)
-      const int64_t n_grid = c.act_list ? std::max<int64_t>(1, (ch.n_pairs + 7) / 8) : ch.n_pairs;
-      const int64_t blocks = c.act_list ? std::min<int64_t>(tpp * n_grid, 4LL * device_cus()) : tpp * n_grid;
+      // with an active-pair list the grid is resident (four workgroups per
+      // CU, fewer if the chunk has fewer tiles) and the workgroups stride over
+      // the listed pairs' tiles (as the streaming Jacobi does)
+      const int64_t blocks =
+          c.act_list ? std::min<int64_t>(tpp * ch.n_pairs, 4LL * device_cus()) : tpp * ch.n_pairs;
       const dim3 grid((unsigned)blocks);
       const bool u8 = g.level == 0, co = g.has_coarse != 0;
       auto go = [&](auto kern) {
