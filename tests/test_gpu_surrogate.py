@@ -283,6 +283,32 @@ def test_gate_routing_and_residual():
         assert torch.equal(mix[k], ref)
 
 
+def test_fallback_counts_route_bitwise():
+    """Thresholds that send 1, 4, 9 and all 16 pairs to the plain solver (the
+    streaming Jacobi then chooses its row bands on the device from the listed
+    count, short bands for few pairs and tall ones for many): every
+    fallen-back pair equals the plain flow bit for bit and every kept pair
+    the network's flow."""
+    need_gpu()
+    W, H, n = 320, 240, 17
+    tab, job = _pairs_table(W, H, n, 21)
+    master, _ = _master(_params(5))
+    net = scn.net_pack(master)
+    prm = scn.flow_params(levels=3)
+    (plain,) = scn.flow([job], prm)
+    (net_only,) = scn.surrogate_infer([job], net)
+    _, _, (res,) = scn.flow_surrogate([job], net, 1e30, prm)
+    r = np.sort(res.cpu().numpy())
+    assert len(r) == n - 1 and r[0] > 0
+    for k in (1, 4, 9, 16):
+        tau = float(r[len(r) - k]) * (1 - 1e-6) if k < len(r) else 0.0
+        (mix,), (fb,), _ = scn.flow_surrogate([job], net, tau, prm)
+        fb = fb.cpu().numpy()
+        assert int(fb.sum()) == k, (k, fb)
+        for q in range(n - 1):
+            assert torch.equal(mix[q], plain[q] if fb[q] else net_only[q]), (k, q)
+
+
 def test_stencil_before_sampling_gate_routing():
     """The surrogate path over original-neighbour pairs (s, s+1): tau = 0
     returns the plain flow of those pairs bit for bit, tau = inf the
