@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // per lane.  BLDS stages the whole weight tensor in LDS as well.
 // MFMA part of the LDS-tiled forward convolution, shared by the kernels that
 // stage a tile: `tile` holds the layer's input tile (SH x SW stored pixels,
-// channel stride CI + 8), `wf` the forward weights [tap][co][ci] (LDS or
+// channel stride tile_cp(L)), `wf` the forward weights [tap][co][ci] (LDS or
 // global).  Each wave owns 16 * MR output pixels (MR pixel blocks of 16 along
 // a row) x all output channels; the epilogue adds the bias, applies ReLU and
 // stores 4 consecutive channels per lane.
@@ -174,6 +174,10 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const bf16_t* __restrict__ x, 
 // in r >> SH: the 16 rows of a read then hit 16 distinct 4-bank groups.
 constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
 constexpr int log2_i(int v) { return v <= 1 ? 0 : 1 + log2_i(v / 2); }
+// Channel stride of a staged input tile: 8 channels of padding, 16 for the
+// last layer (32 input channels), whose tile reads run faster with it.
+constexpr int tile_cp(int l) { return kNet[l].ci + (l == kLayers - 1 ? 16 : 8); }
+
 template <int CI> struct WSwz {
   static constexpr int P = 256 / gcd_i(256, 2 * CI);
   static constexpr int SH = log2_i(P), MASK = 16 / P - 1;
@@ -189,7 +193,7 @@ __device__ __forceinline__ void conv_tile_mma(const bf16_t* __restrict__ tile, c
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16, NCB = CI / 32;
   constexpr bool UP = D.up != 0, RELU = D.relu != 0;
-  constexpr int CP = CI + 8;
+  constexpr int CP = tile_cp(L);
   constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
@@ -360,7 +364,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv_fwd_lds(const bf16_t* __res
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO), NB = COP / 16, NCB = CI / 32;
   constexpr bool UP = D.up != 0, RELU = D.relu != 0;
-  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = tile_cp(L);
   constexpr int BPR = TOW / 16, NBLK = TOH * BPR, MR = NBLK / NWAVE;
   constexpr int NT = 64 * NWAVE;
   constexpr int WELEMS = BLDS ? 9 * COP * CI : 8;
@@ -434,7 +438,7 @@ __global__ void __launch_bounds__(64 * NWAVE, WPE) k_conv_fwd_pers(const bf16_t*
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, COP = cpad(CO);
   constexpr bool UP = D.up != 0;
-  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = CI + 8;
+  constexpr int IH = (TOH - 1) * S + 3, IW = (TOW - 1) * S + 3, CP = tile_cp(L);
   constexpr int NT = 64 * NWAVE;
   constexpr int WELEMS = 9 * COP * CI;
   static_assert(CI % 32 == 0 && TOW % 16 == 0 && (TOH * TOW / 16) % NWAVE == 0, "tile shape");
