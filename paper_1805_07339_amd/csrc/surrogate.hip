@@ -1689,10 +1689,12 @@ template <int L> struct FwdTile {
   static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
   static constexpr bool PERS = (L == 3 || L == 4);
   // waves per SIMD the persistent kernel is compiled for (register budget
-  // 512 / WPE): conv5 runs two 8-wave workgroups per CU, conv4 one
-  static constexpr int WPE = L == 4 ? 4 : 2;
+  // 512 / WPE): conv5 runs two 4-wave workgroups per CU (four pixel blocks
+  // per wave, so each weight fragment read from LDS feeds more MFMAs), conv4
+  // one 8-wave workgroup
+  static constexpr int WPE = 2;
   static constexpr int TOH = kNet[L].stride == 2 ? 4 : (L == 5 ? 16 : 8), TOW = L == 2 ? 16 : 32;
-  static constexpr int NWAVE = (L == 5 || L == 3 || L == 4) ? 8 : (L == 2 ? 2 : 4);
+  static constexpr int NWAVE = (L == 5 || L == 3) ? 8 : (L == 4 ? 4 : (L == 2 ? 2 : 4));
 };
 
 constexpr const char* kFwdTimer[kLayers] = {"conv_fwd1", "conv_fwd2", "conv_fwd3", "conv_fwd4", "conv_fwd5",
