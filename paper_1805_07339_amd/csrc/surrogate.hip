@@ -1675,16 +1675,16 @@ CGeom layer_geom(const NetDims& d, int l, int64_t n) {
 constexpr int kMR = 2;  // 16-pixel row blocks per wave
 
 // Output tile (rows x columns), waves per workgroup and weights-in-LDS choice
-// of the LDS-tiled forward kernel per layer (measured on the 1080p batch):
-// conv4, conv5 and conv6 keep the whole weight tensor in LDS (conv4's 110 KB
-// next to its quarter-size upsampled input tile); conv6 uses a 16 x 32
-// output tile with 8 waves, conv4 and conv5 8 x 32 with 8 waves (two pixel
-// blocks per wave: conv5 then fits 128 VGPRs and runs four waves per SIMD,
-// 9% faster than four waves of four blocks), the others 8 x 32 (4 x 32 for
-// stride 2) with 4 waves; conv3 has a kernel of its own.  conv4 and conv5 run
-// persistent (one workgroup per resident slot, weights staged once, next
-// input tile loaded while the current one is multiplied); conv6, whose
-// weights are small, is faster with one workgroup per tile.
+// of the LDS-tiled forward kernel per layer (chosen by timing on the 1080p
+// batch): conv4, conv5 and conv6 keep the whole weight tensor in LDS (conv4's
+// 110 KB next to its quarter-size upsampled input tile); conv6 uses a 16 x 32
+// output tile with 8 waves, conv4 8 x 32 with 8 waves (two pixel blocks per
+// wave), conv5 8 x 32 with 4 waves (four blocks per wave, two workgroups per
+// CU), the others 8 x 32 (4 x 32 for stride 2) with 4 waves; conv3 has a
+// kernel of its own.  conv4 and conv5 run persistent (one workgroup per
+// resident slot, weights staged once, next input tile loaded while the
+// current one is multiplied); conv6, whose weights are small, is faster with
+// one workgroup per tile.
 template <int L> struct FwdTile {
   static constexpr bool BLDS = (L == 3 || L == 4 || L == 5);
   static constexpr bool PERS = (L == 3 || L == 4);
