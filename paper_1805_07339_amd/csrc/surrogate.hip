@@ -945,25 +945,49 @@ __global__ void __launch_bounds__(256) k_conv_dx(const void* __restrict__ dy, co
 
 // previous layer's output gradient: adjoint of the x2 upsampling (if any),
 // times the ReLU derivative of the stored activation, rounded to BF16.
+// One thread per 8 consecutive channels of one pixel (channel counts are
+// multiples of 8): two 16-byte loads per FP32 row of 8 (four rows under the
+// upsampling adjoint), one 16-byte load of the activation, one 16-byte store.
 __global__ void k_dx_post(const float* __restrict__ dxe, const bf16_t* __restrict__ act, bf16_t* __restrict__ gout,
-                          int64_t n_elems, int32_t h, int32_t w, int32_t c, int32_t up) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n_elems) return;
-  float v;
+                          int64_t n_groups, int32_t h, int32_t w, int32_t c, int32_t up) {
+  const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gi >= n_groups) return;
+  const int32_t g8 = c >> 3;
+  const int64_t p = gi / g8;  // pixel (n, y, x) at the gradient's resolution
+  const int32_t ch = (int32_t)(gi - p * g8) << 3;
+  typedef float f32x4_t __attribute__((ext_vector_type(4)));
+  auto row8 = [&](int64_t off, float (&r)[8]) {
+    const f32x4_t lo = *reinterpret_cast<const f32x4_t*>(dxe + off);
+    const f32x4_t hi = *reinterpret_cast<const f32x4_t*>(dxe + off + 4);
+    r[0] = lo.x; r[1] = lo.y; r[2] = lo.z; r[3] = lo.w;
+    r[4] = hi.x; r[5] = hi.y; r[6] = hi.z; r[7] = hi.w;
+  };
+  float v[8];
   if (up) {
-    const int32_t ch = (int32_t)(i % c);
-    const int64_t p = i / c;
-    const int32_t xx = (int32_t)(p % w);
-    const int64_t t = p / w;
-    const int32_t yy = (int32_t)(t % h);
-    const int64_t n = t / h;
+    const int64_t t = p / w, n = t / h;
+    const int32_t xx = (int32_t)(p - t * w), yy = (int32_t)(t - n * h);
     const int64_t W2 = 2 * (int64_t)w, H2 = 2 * (int64_t)h;
     const int64_t b = ((n * H2 + 2 * yy) * W2 + 2 * xx) * c + ch;
-    v = (dxe[b] + dxe[b + c]) + (dxe[b + W2 * c] + dxe[b + W2 * c + c]);
+    float r00[8], r01[8], r10[8], r11[8];
+    row8(b, r00);
+    row8(b + c, r01);
+    row8(b + W2 * c, r10);
+    row8(b + W2 * c + c, r11);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (r00[k] + r01[k]) + (r10[k] + r11[k]);
   } else {
-    v = dxe[i];
+    row8(p * c + ch, v);
   }
-  gout[i] = bf2f(act[i]) > 0.f ? f2bf(v) : (bf16_t)0;
+  const uint4 a = *reinterpret_cast<const uint4*>(act + p * c + ch);
+  const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bf16_t lo = bf2f((bf16_t)(aw[k] & 0xFFFFu)) > 0.f ? f2bf(v[2 * k]) : (bf16_t)0;
+    const bf16_t hi = bf2f((bf16_t)(aw[k] >> 16)) > 0.f ? f2bf(v[2 * k + 1]) : (bf16_t)0;
+    o[k] = (uint32_t)lo | ((uint32_t)hi << 16);
+  }
+  *reinterpret_cast<uint4*>(gout + p * c + ch) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1863,8 +1887,13 @@ scn_status dx_post(const float* dxe, const bf16_t* act, bf16_t* gout, const NetD
                    int up, hipStream_t s) {
   // l_prev_out: index of the stored activation (layer output l_prev_out) the gradient belongs to
   const int32_t h = d.hl[l_prev_out + 1], w = d.wl[l_prev_out + 1], c = kNet[l_prev_out].co;
-  const int64_t ne = n * h * w * c;
-  hipLaunchKernelGGL(k_dx_post, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, dxe, act, gout, ne, h, w, c, up);
+  static_assert(kNet[0].co % 8 == 0 && kNet[1].co % 8 == 0 && kNet[2].co % 8 == 0 && kNet[3].co % 8 == 0 &&
+                    kNet[4].co % 8 == 0,
+                "k_dx_post takes 8 channels per thread");
+  const int64_t groups = n * h * w * (c / 8);
+  if ((groups + 255) / 256 > 0x7FFFFFFF) { set_error("surrogate batch too large"); return SCN_EUNSUPPORTED; }
+  hipLaunchKernelGGL(k_dx_post, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, dxe, act, gout, groups, h, w,
+                     c, up);
   SCN_LAUNCHED("input-gradient post launch");
   return SCN_OK;
 }
