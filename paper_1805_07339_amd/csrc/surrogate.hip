@@ -1696,7 +1696,7 @@ CGeom layer_geom(const NetDims& d, int l, int64_t n) {
   return g;
 }
 
-constexpr int kMR = 2;  // 16-pixel row blocks per wave
+constexpr int kMR = 4;  // 16-pixel row blocks per wave (conv1 forward in training, input gradients)
 
 // Output tile (rows x columns), waves per workgroup and weights-in-LDS choice
 // of the LDS-tiled forward kernel per layer (chosen by timing on the 1080p
