@@ -840,12 +840,18 @@ __global__ void __launch_bounds__(64 * NWAVE) k_conv12s(const FrameDesc* __restr
 
 // ---------------------------------------------------------------------------
 // input gradient of the effective input: dxe[m][ci] = sum_{tap, co} W[tap][co][ci] dy(out(m, tap))[co]
-template <int L, int MR>
+template <int L, int MR, bool FUSE>
 __global__ void __launch_bounds__(256) k_conv_dx(const void* __restrict__ dy, const uint8_t* __restrict__ blob,
-                                                 float* __restrict__ dxe, CGeom g) {
+                                                 float* __restrict__ dxe, CGeom g, const bf16_t* __restrict__ act,
+                                                 bf16_t* __restrict__ gout) {
   constexpr LayerDef D = kNet[L];
   constexpr int CI = D.ci, CO = D.co, S = D.stride, NB = CI / 16;
   static_assert(CI % 16 == 0, "input-gradient kernel needs ci % 16 == 0");
+  // FUSE (layers that read their input without upsampling): the previous
+  // layer's output gradient is formed here -- times the ReLU derivative of
+  // its stored activation `act`, rounded to BF16 into `gout` -- instead of
+  // going through dxe and k_dx_post (the same values)
+  static_assert(!FUSE || !D.up, "the upsampling adjoint needs k_dx_post");
   const bf16_t* wt = reinterpret_cast<const bf16_t*>(blob + blob_tr_off(L));
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
@@ -939,7 +945,10 @@ __global__ void __launch_bounds__(256) k_conv_dx(const void* __restrict__ dy, co
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t m = base + mr * 16 + kg * 4 + i;
-        if (m < M) dxe[m * CI + nb * 16 + r16] = acc[mr][nb][i];
+        if (m >= M) continue;
+        const int64_t o = m * CI + nb * 16 + r16;
+        if constexpr (FUSE) gout[o] = bf2f(act[o]) > 0.f ? f2bf(acc[mr][nb][i]) : (bf16_t)0;
+        else dxe[o] = acc[mr][nb][i];
       }
 }
 
@@ -1805,12 +1814,21 @@ scn_status launch_fwd(const bf16_t* x, const uint8_t* blob, void* y, const CGeom
 }
 
 template <int L>
-scn_status launch_dx(const void* dy, const uint8_t* blob, float* dxe, const CGeom& g, hipStream_t s) {
+scn_status launch_dx(const void* dy, const uint8_t* blob, float* dxe, const CGeom& g, hipStream_t s,
+                     const bf16_t* act = nullptr, bf16_t* gout = nullptr) {
   const int64_t M = (int64_t)g.n * g.he * g.we;
   const int64_t per_wg = 4 * 16 * kMR;
   const int64_t grid = (M + per_wg - 1) / per_wg;
   KernelTimer timer("conv_dx", s);
-  hipLaunchKernelGGL((k_conv_dx<L, kMR>), dim3((unsigned)grid), dim3(256), 0, s, dy, blob, dxe, g);
+  if constexpr (!kNet[L].up) {
+    if (gout) {
+      hipLaunchKernelGGL((k_conv_dx<L, kMR, true>), dim3((unsigned)grid), dim3(256), 0, s, dy, blob, dxe, g, act,
+                         gout);
+      SCN_LAUNCHED("conv input-gradient launch");
+      return SCN_OK;
+    }
+  }
+  hipLaunchKernelGGL((k_conv_dx<L, kMR, false>), dim3((unsigned)grid), dim3(256), 0, s, dy, blob, dxe, g, act, gout);
   SCN_LAUNCHED("conv input-gradient launch");
   return SCN_OK;
 }
@@ -1903,8 +1921,7 @@ scn_status net_backward(const NetDims& d, int64_t n, const uint8_t* blob, const 
   scn_status st;
   // conv6: dy = ghalf (FP32), input act5
   if ((st = launch_dw<5>(b.ghalf, b.act[4], b, grads, layer_geom(d, 5, n), s)) != SCN_OK) return st;
-  if ((st = launch_dx<5>(b.ghalf, blob, b.dxe, layer_geom(d, 5, n), s)) != SCN_OK) return st;
-  if ((st = dx_post(b.dxe, b.act[4], b.g[0], d, 4, n, 0, s)) != SCN_OK) return st;
+  if ((st = launch_dx<5>(b.ghalf, blob, b.dxe, layer_geom(d, 5, n), s, b.act[4], b.g[0])) != SCN_OK) return st;
   // conv5: dy = g[0], input up(act4)
   if ((st = launch_dw<4>(b.g[0], b.act[3], b, grads, layer_geom(d, 4, n), s)) != SCN_OK) return st;
   if ((st = launch_dx<4>(b.g[0], blob, b.dxe, layer_geom(d, 4, n), s)) != SCN_OK) return st;
@@ -1915,12 +1932,10 @@ scn_status net_backward(const NetDims& d, int64_t n, const uint8_t* blob, const 
   if ((st = dx_post(b.dxe, b.act[2], b.g[0], d, 2, n, 1, s)) != SCN_OK) return st;
   // conv3: dy = g[0], input act2 (stride 2)
   if ((st = launch_dw<2>(b.g[0], b.act[1], b, grads, layer_geom(d, 2, n), s)) != SCN_OK) return st;
-  if ((st = launch_dx<2>(b.g[0], blob, b.dxe, layer_geom(d, 2, n), s)) != SCN_OK) return st;
-  if ((st = dx_post(b.dxe, b.act[1], b.g[1], d, 1, n, 0, s)) != SCN_OK) return st;
+  if ((st = launch_dx<2>(b.g[0], blob, b.dxe, layer_geom(d, 2, n), s, b.act[1], b.g[1])) != SCN_OK) return st;
   // conv2: dy = g[1], input act1 (stride 2)
   if ((st = launch_dw<1>(b.g[1], b.act[0], b, grads, layer_geom(d, 1, n), s)) != SCN_OK) return st;
-  if ((st = launch_dx<1>(b.g[1], blob, b.dxe, layer_geom(d, 1, n), s)) != SCN_OK) return st;
-  if ((st = dx_post(b.dxe, b.act[0], b.g[0], d, 0, n, 0, s)) != SCN_OK) return st;
+  if ((st = launch_dx<1>(b.g[1], blob, b.dxe, layer_geom(d, 1, n), s, b.act[0], b.g[0])) != SCN_OK) return st;
   // conv1: dy = g[0], input x
   return launch_dw<0>(b.g[0], b.x, b, grads, layer_geom(d, 0, n), s);
 }
