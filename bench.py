@@ -365,19 +365,27 @@ def surrogate_leg(scn, torch, dev, jobs, hists, ws_hist, plain_flows, stream, m_
             "forced_fallback": forced}
 
 
+def fallback_threshold(sorted_residuals, frac):
+    """Gate threshold under which about `frac` of the pairs fall back (a
+    pair falls back when its residual exceeds the threshold): just below the
+    residual at that quantile, 0 when every pair should fall back."""
+    n = len(sorted_residuals)
+    k = n - int(round(frac * n))  # pairs kept: the k smallest residuals
+    if k == 0:
+        return 0.0
+    return float(sorted_residuals[k]) * (1.0 - 1e-6) if k < n else float("inf")
+
+
 def forced_fallback(scn, torch, step, fbs, res, n_pairs, m_total, base_s, args):
     """The gated step with thresholds below the calibrated one, so that a
     quarter, a half and all of the pairs fall back: what failing pairs cost at
     the benchmark shape (the calibrated threshold keeps every pair here).
     Thresholds are quantiles of the step's own residuals, set just below them
     so that the pairs at the quantile fall back too."""
-    r = torch.cat([x.float() for x in res]).sort().values
+    r = torch.cat([x.float() for x in res]).sort().values.cpu().tolist()
     out = []
     for frac in (0.25, 0.5, 1.0):
-        k = n_pairs - int(round(frac * n_pairs))  # pairs kept: the k smallest residuals
-        t = float(r[k].item()) * (1.0 - 1e-6) if k < n_pairs else float("inf")
-        if k == 0:
-            t = 0.0  # every pair with a non-zero residual falls back
+        t = fallback_threshold(r, frac)
         for _ in range(max(1, args.warmup)):
             step(t)
         torch.cuda.synchronize()

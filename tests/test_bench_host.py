@@ -1,5 +1,5 @@
-"""Host logic of bench.py (no GPU): the multi-GPU refusal and the Jacobi
-roofline arithmetic."""
+"""Host logic of bench.py (no GPU): the multi-GPU refusal, the Jacobi
+roofline arithmetic and the thresholds of the forced-fallback leg."""
 import os
 import subprocess
 import sys
@@ -25,3 +25,16 @@ def test_jacobi_roofline_from_work_units():
     assert abs(r["frac"] - 28.0 / bench.HBM_PEAK_GBS) < 1e-12
     assert abs(r["alu"]["achieved_TFLOPs"] - 27 * 5e9 / 1e12) < 1e-9
     assert r["traffic"] == 3.0e9 and r["avg_launch_ms"] == 100.0
+
+
+def test_fallback_thresholds_select_the_quantiles():
+    import bench
+    import random
+    rng = random.Random(3)
+    for n in (1, 7, 122):
+        r = sorted(rng.uniform(0.5, 4.0) for _ in range(n))
+        for frac in (0.25, 0.5, 1.0):
+            t = bench.fallback_threshold(r, frac)
+            failing = sum(x > t for x in r)  # the gate's rule: residual above the threshold
+            assert failing == int(round(frac * n)), (n, frac, t)
+            assert t >= 0.0
