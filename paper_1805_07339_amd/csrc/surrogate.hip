@@ -1820,6 +1820,10 @@ scn_status launch_dx(const void* dy, const uint8_t* blob, float* dxe, const CGeo
   const int64_t per_wg = 4 * 16 * kMR;
   const int64_t grid = (M + per_wg - 1) / per_wg;
   KernelTimer timer("conv_dx", s);
+  if (kNet[L].up && gout) {
+    set_error("internal: an upsampling layer's input gradient needs the separate post-processing");
+    return SCN_EINVAL;
+  }
   if constexpr (!kNet[L].up) {
     if (gout) {
       hipLaunchKernelGGL((k_conv_dx<L, kMR, true>), dim3((unsigned)grid), dim3(256), 0, s, dy, blob, dxe, g, act,
